@@ -1,0 +1,240 @@
+/*
+ * gc.h -- C ABI of libgc: round-synchronous speculative graph colouring on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The method is the barrier-synchronised parallel colouring of Singhal, Peri
+ * and Kalyanasundaram, "Multi-threaded Graph Coloring Algorithm for Shared
+ * Memory Architecture" (arXiv:1509.08267), Algorithm 1 (Section 3.1), run
+ * with every vertex its own block:
+ *
+ *   round r = 1, 2, ...:
+ *     speculate  every uncoloured vertex takes the least colour not yet final
+ *                on any neighbour (First Fit, Section 3; colours 0-based as
+ *                in Algorithm 1's TotalColors = {0, ..., max degree});
+ *     barrier;
+ *     detect     a vertex loses if a lower-id neighbour, also coloured this
+ *                round, took the same colour (the paper recolours the lower
+ *                partition; numbering partitions by decreasing id gives this
+ *                rule); winners' colours become final;
+ *     barrier;   losers form the next round's set; stop when it is empty.
+ *
+ * The result is a deterministic function of the graph (independent of launch
+ * shape, row order, stream and batching): bit-identical to a plain
+ * single-threaded simulation of the same rounds.  It is a proper colouring
+ * (Lemma 1, Section 4) in which every colour is the least one absent from the
+ * vertex's neighbourhood, so colour(v) <= deg(v) and at most Delta + 1
+ * colours are used (Section 2.1).  Rounds never exceed n (Lemma 2 with
+ * p = n blocks).
+ *
+ * Conventions for every entry point:
+ *   - Graphs are simple and undirected (Section 2.1): CSR with each edge
+ *     stored in both rows, no self-loops, no duplicate entries.  Vertex ids
+ *     are 0-based int32.
+ *   - Array arguments are DEVICE pointers unless stated otherwise, owned by
+ *     the caller.  Calls are asynchronous on `stream` (a hipStream_t; NULL is
+ *     the null stream); results are valid once that stream has synchronised.
+ *   - A negative return value is an error (enum gc_status);
+ *     gc_last_error() describes it.  Nothing throws across this boundary.
+ *   - A GPU fault inside a call is reported as GC_EDEVICE by that call or by
+ *     the next call that synchronises.
+ */
+#ifndef GC_H
+#define GC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gc_ctx *gc_handle; /* opaque, library-owned */
+
+enum gc_status {
+  GC_OK = 0,
+  GC_EINVAL = -1,  /* bad argument or (with GC_VALIDATE) malformed graph   */
+  GC_ENOMEM = -2,  /* device or pinned-host allocation failed              */
+  GC_EDEVICE = -3, /* HIP runtime error or GPU fault                       */
+  GC_EROUNDS = -4, /* round cap (GC_OPT_MAX_ROUNDS) reached before the end */
+  GC_EBUSY = -5,   /* handle already in use by an unfinished call          */
+  GC_ETOOBIG = -6  /* sizes exceed what the library supports               */
+};
+
+enum gc_flags {
+  GC_ROWPTR_I64 = 1u << 0,  /* rowptr is int64 (default int32)              */
+  GC_VALIDATE = 1u << 1,    /* check the CSR on the device in gc_create:
+                               monotone rowptr, rowptr[0] = 0, rowptr[n] = m,
+                               ids in range, no self-loops, no duplicates,
+                               symmetric; rejects with GC_EINVAL           */
+  GC_ROWS_SORTED = 1u << 2  /* caller promises ascending rows; enables the
+                               early stop of the conflict scan and the
+                               O(log deg) symmetry check of GC_VALIDATE     */
+};
+
+/*
+ * gc_create -- bind a graph and allocate the colouring state.
+ *
+ *   out      receives the handle (set to NULL on failure)
+ *   rowptr   device, n + 1 entries, int32 (or int64 with GC_ROWPTR_I64)
+ *   colidx   device, m entries, int32 neighbour ids
+ *   n        vertices, 0 <= n < 2^31
+ *   m        CSR entries = rowptr[n] = 2 |E|
+ *   flags    OR of enum gc_flags
+ *   stream   stream for the set-up work (degree scan, validation)
+ *
+ * The graph arrays are BORROWED: they must stay allocated and unchanged
+ * until gc_destroy.  The library allocates O(n) device scratch (worklists,
+ * counters) and a small pinned host block; it synchronises `stream` before
+ * returning.  The handle belongs to the device current at this call.
+ * Returns GC_OK, GC_EINVAL, GC_ENOMEM, GC_ETOOBIG or GC_EDEVICE.
+ */
+int gc_create(gc_handle *out, const void *rowptr, const int32_t *colidx,
+              int64_t n, int64_t m, uint32_t flags, void *stream);
+
+/*
+ * gc_color -- colour the bound graph.
+ *
+ *   colors_out  device, n int32 entries; receives colour(v) in 0..deg(v).
+ *               It is also the working state during the call (its prior
+ *               contents are ignored).
+ *   stream      all work is queued here; the call returns before the
+ *               colouring is finished except in GC_MODE_HOST, which reads a
+ *               counter back every round.
+ *
+ * One handle serves one call at a time: a second gc_color before the first
+ * has been observed finished (gc_get_stats / stream sync) returns GC_EBUSY
+ * when that can be detected.  Returns GC_OK, GC_EINVAL, GC_EBUSY, GC_EROUNDS
+ * (GC_MODE_HOST only, when GC_OPT_MAX_ROUNDS is reached) or GC_EDEVICE.
+ */
+int gc_color(gc_handle h, int32_t *colors_out, void *stream);
+
+/*
+ * gc_get_stats -- results of the last gc_color on this handle.
+ * Waits for that call's stream.  `rounds` receives the number of rounds R
+ * (0 when n = 0), `num_colors` max colour + 1 (0 when n = 0).  Either
+ * pointer may be NULL.  Returns GC_EROUNDS if the call stopped at the round
+ * cap with vertices still uncoloured.
+ */
+int gc_get_stats(gc_handle h, int64_t *rounds, int32_t *num_colors);
+
+/*
+ * gc_get_round_sizes -- |U_r|, the number of vertices (re)coloured in round
+ * r, for r = 1..min(R, cap) of the last gc_color (host array `sizes`).
+ * `rounds` (may be NULL) receives R.  At most GC_TRACE_ROUNDS rounds are
+ * recorded.  Waits for the last call's stream.
+ */
+#define GC_TRACE_ROUNDS 65536
+int gc_get_round_sizes(gc_handle h, int64_t *sizes, int64_t cap, int64_t *rounds);
+
+/* Tunables.  None changes the result (it is a function of the graph only). */
+enum gc_option {
+  GC_OPT_MODE = 1,           /* enum gc_mode, default GC_MODE_AUTO            */
+  GC_OPT_LANES = 2,          /* lanes per light vertex: 1,2,4,...,64 (def. auto) */
+  GC_OPT_HEAVY_DEGREE = 3,   /* deg > this => a whole workgroup per vertex    */
+  GC_OPT_BLOCKS_PER_CU = 4,  /* grid size of the grid-stride kernels          */
+  GC_OPT_MAX_ROUNDS = 5,     /* stop after this many rounds (debug cap; 0 = none) */
+  GC_OPT_CHUNK_ROUNDS = 6    /* rounds queued per host check in GC_MODE_CHUNKED/GRAPH */
+};
+enum gc_mode {
+  GC_MODE_AUTO = 0,
+  GC_MODE_HOST = 1,       /* one round per host iteration, count read back  */
+  GC_MODE_CHUNKED = 2,    /* rounds queued in chunks, empty rounds exit early */
+  GC_MODE_PERSISTENT = 3, /* one cooperative kernel, device-side round loop  */
+  GC_MODE_GRAPH = 4       /* a captured hipGraph of a chunk of rounds        */
+};
+int gc_set_option(gc_handle h, int option, int64_t value);
+int gc_get_option(gc_handle h, int option, int64_t *value);
+
+/* gc_destroy -- wait for outstanding work, free the handle's scratch.
+ * The borrowed graph arrays are not touched.  NULL is accepted. */
+int gc_destroy(gc_handle h);
+
+/* gc_last_error -- message of the last failure on `h`, or of the calling
+ * thread's last failure when h is NULL (e.g. a failed gc_create).  The
+ * string is owned by the library and valid until the next call. */
+const char *gc_last_error(gc_handle h);
+
+/* ------------------------------------------------------------------ batch --
+ * Many independent graphs coloured in one persistent launch.  Graph g has
+ * n_g = voff[g+1] - voff[g] vertices and nnz_g = eoff[g+1] - eoff[g] CSR
+ * entries; its local rowptr (n_g + 1 int32 entries, starting at 0) begins at
+ * rowptr_local[voff[g] + g] and its local colidx (ids 0..n_g-1) at
+ * colidx_local[eoff[g]].  Each graph is coloured exactly as gc_color would
+ * colour it alone (same bits; the batching never changes a result).
+ */
+
+/*
+ * gc_batch_workspace_bytes -- device workspace needed by gc_color_batch.
+ * voff and eoff are HOST arrays of num_graphs + 1 entries (only sizes are
+ * read).  Returns 0 on bad arguments.
+ */
+size_t gc_batch_workspace_bytes(int64_t num_graphs, const int64_t *voff,
+                                const int64_t *eoff);
+
+/*
+ * gc_color_batch -- colour every graph of a packed batch.
+ *
+ *   voff, eoff      device, int64[num_graphs + 1], non-decreasing, from 0
+ *   rowptr_local    device, int32, sum(n_g + 1) entries (layout above)
+ *   colidx_local    device, int32, sum(nnz_g) entries
+ *   colors_out      device, int32, sum(n_g): colour of local vertex v of
+ *                   graph g at colors_out[voff[g] + v]; also working state
+ *   rounds_out      device, int32[num_graphs] rounds per graph, or NULL
+ *   workspace       device scratch of at least gc_batch_workspace_bytes
+ *                   (caller-owned; contents on entry are ignored)
+ *
+ * Each graph must satisfy the gc_create preconditions with sorted rows.
+ * Returns GC_OK, GC_EINVAL (bad sizes or too small a workspace) or
+ * GC_EDEVICE.  Asynchronous on `stream`.
+ */
+int gc_color_batch(int64_t num_graphs, const int64_t *voff, const int64_t *eoff,
+                   const int32_t *rowptr_local, const int32_t *colidx_local,
+                   int32_t *colors_out, int32_t *rounds_out, void *workspace,
+                   size_t workspace_bytes, void *stream);
+
+/*
+ * Resumable batch steps for continuous batching.  A graph's whole state
+ * between rounds is its colour array (final colours >= 0; a negative entry
+ * marks a vertex still to be coloured) plus the count of rounds done, so a
+ * colouring can be advanced a few rounds at a time, with graphs joining and
+ * leaving between steps, and still give the same bits as one gc_color call.
+ *
+ * gc_graph_desc (device array, one per graph in the step):
+ *   rowptr_off   index into rowptr_base of the graph's local rowptr
+ *   colidx_off   index into colidx_base of its local colidx
+ *   color_off    index into colors_base of its colour/state array
+ *   n            vertices of the graph
+ *   rounds       in: rounds already done (0 = fresh: the state is
+ *                initialised); out: rounds done after the step
+ *   active       out: vertices still uncoloured after the step (0 = done)
+ */
+typedef struct gc_graph_desc {
+  int64_t rowptr_off;
+  int64_t colidx_off;
+  int64_t color_off;
+  int32_t n;
+  int32_t rounds;
+  int32_t active;
+  int32_t max_degree; /* in: max degree of the graph (sizes state encodings) */
+} gc_graph_desc;
+
+/*
+ * gc_batch_step -- advance each listed graph by at most `max_rounds` rounds
+ * (0 = until done).  `descs` is a device array of num_graphs entries;
+ * `workspace` at least gc_batch_step_workspace_bytes(num_graphs,
+ * max_vertices) bytes, where max_vertices bounds every n.  Asynchronous on
+ * `stream`.
+ */
+size_t gc_batch_step_workspace_bytes(int64_t num_graphs, int64_t total_vertices);
+int gc_batch_step(int64_t num_graphs, gc_graph_desc *descs,
+                  const int32_t *rowptr_base, const int32_t *colidx_base,
+                  int32_t *colors_base, int32_t max_rounds, void *workspace,
+                  size_t workspace_bytes, void *stream);
+
+/* Library version, "major.minor.patch". */
+const char *gc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GC_H */

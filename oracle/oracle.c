@@ -1,0 +1,257 @@
+/*
+ * oracle.c -- CPU oracle for round-synchronous speculative colouring.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this code.  The GPU library
+ * shares nothing with it: no headers, no helpers, no tables.
+ *
+ * It is deliberately plain, single-threaded and slow, and follows the
+ * paper step by step:
+ *
+ *   oracle_rsc  -- Algorithm 1 (Section 3.1, "Using Barrier Synchronisation")
+ *                  with every vertex its own block (p = n), so every
+ *                  non-isolated vertex is a boundary vertex:
+ *                    phase 1: each vertex still to be coloured takes the
+ *                             least colour not used by a neighbour (First
+ *                             Fit, Section 3); colours are 0-based, drawn
+ *                             from {0, ..., max degree} (Algorithm 1's
+ *                             TotalColors);
+ *                    barrier;
+ *                    phase 2: conflicts between two vertices coloured in the
+ *                             same round are detected; one side is recoloured
+ *                             in the next round;
+ *                    barrier; repeat while some vertex must be recoloured.
+ *                  Readings taken where the paper is silent or garbled:
+ *                    - the HIGHER vertex id of a conflicting pair is
+ *                      recoloured (the paper recolours the vertex in the
+ *                      lower partition; with one vertex per partition that
+ *                      is the same rule with partitions numbered by
+ *                      decreasing id);
+ *                    - the set of vertices to recolour collects the vertex
+ *                      v under test (the pseudo-code's "R_i <- R_i U {u}"
+ *                      names the foreign vertex; the text and both lemmas of
+ *                      Section 4 recolour the vertex of the losing block);
+ *                    - phase 1 sees only colours that are final (committed
+ *                      in an earlier round); a neighbour that is itself
+ *                      waiting to be recoloured forbids nothing;
+ *                    - all vertices start uncoloured (ForbiddenColors
+ *                      initialised to -1), so round 1 colours every vertex 0.
+ *
+ *   oracle_seq  -- the sequential First-Fit baseline of Section 5 (vertex
+ *                  order 0, 1, ..., n-1; the paper does not state the order).
+ *
+ *   oracle_check_* -- what the problem statement (Section 2.1) and Lemma 1
+ *                  (Section 4) fix: a proper colouring, and First-Fit's
+ *                  Grundy property (each colour is the least one absent from
+ *                  its neighbourhood).
+ *
+ * Graphs are CSR with int64 rowptr and int32 colidx; rows need not be
+ * sorted.  Nothing here allocates more than O(n + max degree).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* least c >= 0 with used[c] == 0, where used has length len; len itself
+ * when all of 0..len-1 are used */
+static int32_t least_absent(const unsigned char *used, int64_t len) {
+  int64_t c = 0;
+  while (c < len && used[c]) ++c;
+  return (int32_t)c;
+}
+
+/*
+ * Round-synchronous speculative colouring (Algorithm 1, p = n).
+ *
+ * color_out[n]     final colours
+ * round_out[n]     (may be NULL) the round in which each vertex's colour
+ *                  became final, 1-based
+ * trace[3*cap]     (may be NULL) per round r (0-based slot r-1):
+ *                    trace[3(r-1)+0] = |U_r|       vertices coloured in round r
+ *                    trace[3(r-1)+1] = sum of deg(v) over U_r
+ *                    trace[3(r-1)+2] = sum over U_r of #neighbours u < v
+ * returns the number of rounds R (0 when n == 0), or -1 on bad arguments
+ * or allocation failure.  Rounds beyond `cap` are not traced.
+ */
+int64_t oracle_rsc(int64_t n, const int64_t *rowptr, const int32_t *colidx,
+                   int32_t *color_out, int32_t *round_out, int64_t *trace,
+                   int64_t cap) {
+  if (n < 0 || (n > 0 && (!rowptr || !color_out))) return -1;
+  if (n == 0) return 0;
+  int64_t maxdeg = 0;
+  for (int64_t v = 0; v < n; ++v) {
+    int64_t d = rowptr[v + 1] - rowptr[v];
+    if (d < 0) return -1;
+    if (d > maxdeg) maxdeg = d;
+  }
+  int32_t *color = color_out;          /* -1 = not final yet            */
+  int32_t *tent = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+  unsigned char *inU = (unsigned char *)calloc((size_t)n, 1);
+  unsigned char *lose = (unsigned char *)calloc((size_t)n, 1);
+  int64_t *U = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+  unsigned char *used = (unsigned char *)calloc((size_t)maxdeg + 1, 1);
+  if (!tent || !inU || !lose || !U || !used) {
+    free(tent); free(inU); free(lose); free(U); free(used);
+    return -1;
+  }
+  /* Initialisation: nothing is coloured, U = V. */
+  int64_t nU = n;
+  for (int64_t v = 0; v < n; ++v) {
+    color[v] = -1;
+    U[v] = v;
+    inU[v] = 1;
+    if (round_out) round_out[v] = 0;
+  }
+  int64_t r = 0;
+  while (nU > 0) {
+    ++r;
+    /* Phase 1 (tentative colouring): least colour not final on a neighbour.
+     * Only colours 0..deg(v) can matter, since at most deg(v) are used. */
+    for (int64_t i = 0; i < nU; ++i) {
+      int64_t v = U[i];
+      int64_t d = rowptr[v + 1] - rowptr[v];
+      for (int64_t k = rowptr[v]; k < rowptr[v + 1]; ++k) {
+        int32_t c = color[colidx[k]];
+        if (c >= 0 && c <= d) used[c] = 1;
+      }
+      tent[v] = least_absent(used, d + 1);
+      for (int64_t k = rowptr[v]; k < rowptr[v + 1]; ++k) {
+        int32_t c = color[colidx[k]];
+        if (c >= 0 && c <= d) used[c] = 0;
+      }
+    }
+    /* (barrier) Phase 2 (conflict detection): v is recoloured when a
+     * neighbour u of lower id, also coloured in this round, took the same
+     * colour. */
+    int64_t sdeg = 0, slow = 0;
+    for (int64_t i = 0; i < nU; ++i) {
+      int64_t v = U[i];
+      lose[v] = 0;
+      sdeg += rowptr[v + 1] - rowptr[v];
+      for (int64_t k = rowptr[v]; k < rowptr[v + 1]; ++k) {
+        int64_t u = colidx[k];
+        if (u < v) ++slow;
+        if (inU[u] && u < v && tent[u] == tent[v]) lose[v] = 1;
+      }
+    }
+    if (trace && r <= cap) {
+      trace[3 * (r - 1) + 0] = nU;
+      trace[3 * (r - 1) + 1] = sdeg;
+      trace[3 * (r - 1) + 2] = slow;
+    }
+    /* Colours of the vertices that did not lose become final; the losers
+     * form the next round's set (kept in ascending order). */
+    for (int64_t i = 0; i < nU; ++i) {
+      int64_t v = U[i];
+      if (!lose[v]) {
+        color[v] = tent[v];
+        if (round_out) round_out[v] = (int32_t)r;
+      }
+    }
+    int64_t w = 0;
+    for (int64_t i = 0; i < nU; ++i) {
+      int64_t v = U[i];
+      if (lose[v]) U[w++] = v;
+      else inU[v] = 0;
+    }
+    nU = w;
+    /* (barrier) */
+  }
+  free(tent); free(inU); free(lose); free(U); free(used);
+  return r;
+}
+
+/* Sequential First Fit in id order: color[v] = least colour not used by a
+ * neighbour u < v.  Returns 0, or -1 on bad arguments. */
+int oracle_seq(int64_t n, const int64_t *rowptr, const int32_t *colidx,
+               int32_t *color) {
+  if (n < 0 || (n > 0 && (!rowptr || !color))) return -1;
+  int64_t maxdeg = 0;
+  for (int64_t v = 0; v < n; ++v) {
+    int64_t d = rowptr[v + 1] - rowptr[v];
+    if (d > maxdeg) maxdeg = d;
+  }
+  unsigned char *used = (unsigned char *)calloc((size_t)maxdeg + 1, 1);
+  if (!used) return -1;
+  for (int64_t v = 0; v < n; ++v) {
+    int64_t d = rowptr[v + 1] - rowptr[v];
+    for (int64_t k = rowptr[v]; k < rowptr[v + 1]; ++k) {
+      int64_t u = colidx[k];
+      if (u < v && color[u] <= d) used[color[u]] = 1;
+    }
+    color[v] = least_absent(used, d + 1);
+    for (int64_t k = rowptr[v]; k < rowptr[v + 1]; ++k) {
+      int64_t u = colidx[k];
+      if (u < v && color[u] <= d) used[color[u]] = 0;
+    }
+  }
+  free(used);
+  return 0;
+}
+
+/* Number of CSR entries (v, u) with color[v] == color[u], plus the number of
+ * vertices with a negative colour.  0 means a proper colouring
+ * (Section 2.1; Lemma 1 of Section 4). */
+int64_t oracle_check_proper(int64_t n, const int64_t *rowptr,
+                            const int32_t *colidx, const int32_t *color) {
+  int64_t bad = 0;
+  for (int64_t v = 0; v < n; ++v) {
+    if (color[v] < 0) ++bad;
+    for (int64_t k = rowptr[v]; k < rowptr[v + 1]; ++k)
+      if (color[colidx[k]] == color[v]) ++bad;
+  }
+  return bad;
+}
+
+/* Number of vertices whose colour is not the least colour absent from its
+ * neighbourhood (First Fit, Section 3).  0 for every First-Fit colouring
+ * whose vertices all see their final neighbourhood. */
+int64_t oracle_check_grundy(int64_t n, const int64_t *rowptr,
+                            const int32_t *colidx, const int32_t *color) {
+  int64_t maxdeg = 0;
+  for (int64_t v = 0; v < n; ++v) {
+    int64_t d = rowptr[v + 1] - rowptr[v];
+    if (d > maxdeg) maxdeg = d;
+  }
+  unsigned char *used = (unsigned char *)calloc((size_t)maxdeg + 1, 1);
+  if (!used) return -1;
+  int64_t bad = 0;
+  for (int64_t v = 0; v < n; ++v) {
+    int64_t d = rowptr[v + 1] - rowptr[v];
+    for (int64_t k = rowptr[v]; k < rowptr[v + 1]; ++k) {
+      int32_t c = color[colidx[k]];
+      if (c >= 0 && c <= d) used[c] = 1;
+    }
+    if (color[v] != least_absent(used, d + 1)) ++bad;
+    for (int64_t k = rowptr[v]; k < rowptr[v + 1]; ++k) {
+      int32_t c = color[colidx[k]];
+      if (c >= 0 && c <= d) used[c] = 0;
+    }
+  }
+  free(used);
+  return bad;
+}
+
+/* Colour every graph of a packed batch independently with oracle_rsc.
+ * voff/eoff are the per-graph vertex and CSR-entry offsets; graph g's local
+ * rowptr (n_g + 1 int32 entries) starts at rowptr_local[voff[g] + g], its
+ * local colidx at colidx_local[eoff[g]].  colors_out[voff[g] + v] receives
+ * the colour of local vertex v; rounds_out[g] the round count.  Returns 0,
+ * or -1 on failure. */
+int oracle_rsc_batch(int64_t G, const int64_t *voff, const int64_t *eoff,
+                     const int32_t *rowptr_local, const int32_t *colidx_local,
+                     int32_t *colors_out, int64_t *rounds_out) {
+  for (int64_t g = 0; g < G; ++g) {
+    int64_t n = voff[g + 1] - voff[g];
+    const int32_t *rp32 = rowptr_local + voff[g] + g;
+    int64_t *rp = (int64_t *)malloc(((size_t)n + 1) * sizeof(int64_t));
+    if (!rp) return -1;
+    for (int64_t v = 0; v <= n; ++v) rp[v] = rp32[v];
+    int64_t R = oracle_rsc(n, rp, colidx_local + eoff[g], colors_out + voff[g],
+                           NULL, NULL, 0);
+    free(rp);
+    if (R < 0) return -1;
+    if (rounds_out) rounds_out[g] = R;
+  }
+  return 0;
+}

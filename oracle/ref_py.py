@@ -1,0 +1,110 @@
+"""Second, independent oracle in pure Python, for tiny graphs only.
+
+TEST INFRASTRUCTURE ONLY.  Written separately from ``oracle.c`` from the same
+passages, so that a slip in one is caught by the other:
+
+* ``rsc`` -- Algorithm 1 (Section 3.1) with one vertex per block: each round
+  every uncoloured vertex takes the least colour absent from its coloured
+  neighbours (First Fit, Section 3); then of each pair of adjacent vertices
+  that took the same colour this round the higher id is recoloured; repeat.
+  Neighbours still waiting for a colour forbid nothing.
+* ``seq`` -- sequential First Fit in id order (Section 5 baseline).
+* ``chromatic_number`` -- brute force over all colourings, for n <= 10,
+  the quantity the paper's objective minimises (Section 2.1).
+
+Graphs are adjacency lists: ``adj[v]`` is an iterable of neighbours.
+"""
+from __future__ import annotations
+
+import itertools
+
+
+def adjacency(rowptr, colidx):
+    n = len(rowptr) - 1
+    return [[int(u) for u in colidx[int(rowptr[v]):int(rowptr[v + 1])]] for v in range(n)]
+
+
+def mex(values) -> int:
+    s = set(values)
+    c = 0
+    while c in s:
+        c += 1
+    return c
+
+
+def rsc(adj):
+    """Returns (colours, rounds, round_of)."""
+    n = len(adj)
+    final = {}            # v -> colour, once final
+    round_of = [0] * n
+    waiting = set(range(n))
+    rounds = 0
+    while waiting:
+        rounds += 1
+        trial = {v: mex(final[u] for u in adj[v] if u in final) for v in waiting}
+        losers = {v for v in waiting
+                  if any(u in waiting and u < v and trial[u] == trial[v] for u in adj[v])}
+        for v in waiting - losers:
+            final[v] = trial[v]
+            round_of[v] = rounds
+        waiting = losers
+    return [final[v] for v in range(n)], rounds, round_of
+
+
+def seq(adj):
+    n = len(adj)
+    col = [None] * n
+    for v in range(n):
+        col[v] = mex(col[u] for u in adj[v] if u < v)
+    return col
+
+
+def is_proper(adj, col) -> bool:
+    return all(col[v] != col[u] for v in range(len(adj)) for u in adj[v])
+
+
+def chromatic_number(adj) -> int:
+    """Smallest k admitting a proper colouring, by exhaustive search.
+
+    Every assignment of k colours is enumerated by depth-first search over
+    vertices 0..n-1, cutting a branch as soon as an edge is monochromatic and
+    naming colours in order of first use (a relabelling of colour classes
+    never changes properness)."""
+    n = len(adj)
+    if n == 0:
+        return 0
+    if n > 10:
+        raise ValueError("brute force is for n <= 10")
+    col = [-1] * n
+
+    def extend(v, k, used):
+        if v == n:
+            return True
+        for c in range(min(used + 1, k)):
+            if all(col[u] != c for u in adj[v] if u < v):
+                col[v] = c
+                if extend(v + 1, k, max(used, c + 1)):
+                    return True
+                col[v] = -1
+        return False
+
+    for k in range(1, n + 1):
+        if extend(0, k, 0):
+            return k
+    return n
+
+
+def chromatic_number_exhaustive(adj) -> int:
+    """The same quantity by plain enumeration of all k^n assignments (n <= 7),
+    to check the pruned search above."""
+    n = len(adj)
+    if n == 0:
+        return 0
+    if n > 7:
+        raise ValueError("plain enumeration is for n <= 7")
+    edges = [(v, u) for v in range(n) for u in adj[v] if v < u]
+    for k in range(1, n + 1):
+        for col in itertools.product(range(k), repeat=n):
+            if all(col[a] != col[b] for a, b in edges):
+                return k
+    return n

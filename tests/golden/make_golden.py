@@ -1,0 +1,90 @@
+"""Write ``workloads.json``: the oracle's answers on the full-size workloads.
+
+Every value in the output comes from ``graphgen`` (the inputs) and ``oracle``
+(the answers) only.  Run from the repository root:
+
+    python tests/golden/make_golden.py [workload ...]
+
+Per workload it records the input's SHA-256 and shape, the oracle's round
+count, colour count and the SHA-256 of its colour vector, the per-round
+totals used for algorithmic byte counts (sum over rounds of |U_r|, of the
+degrees of U_r and of the lower-neighbour counts of U_r), the sequential
+First-Fit colour count, and the oracle's single-thread time.
+"""
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import graphgen  # noqa: E402
+import oracle  # noqa: E402
+
+OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "workloads.json")
+
+
+def colors_sha(c: np.ndarray) -> str:
+    return hashlib.sha256(np.ascontiguousarray(c, dtype=np.int32).tobytes()).hexdigest()
+
+
+def one(name):
+    inp = graphgen.workload(name)
+    rec = {"description": graphgen.WORKLOADS[name]}
+    if isinstance(inp, graphgen.Batch):
+        rec.update(input_sha256=inp.sha256(), num_graphs=inp.num_graphs,
+                   n=int(inp.voff[-1]), nnz=int(inp.eoff[-1]))
+        t = time.perf_counter()
+        colors, rounds = oracle.rsc_batch(inp.voff, inp.eoff, inp.rowptr_local, inp.colidx_local)
+        rec["oracle_seconds"] = time.perf_counter() - t
+        rec["colors_sha256"] = colors_sha(colors)
+        rec["rounds_sha256"] = hashlib.sha256(rounds.astype(np.int64).tobytes()).hexdigest()
+        rec["rounds_max"] = int(rounds.max())
+        rec["rounds_sum"] = int(rounds.sum())
+        ncol = np.zeros(inp.num_graphs, np.int64)
+        for g in range(inp.num_graphs):
+            a, b = int(inp.voff[g]), int(inp.voff[g + 1])
+            ncol[g] = int(colors[a:b].max()) + 1 if b > a else 0
+        rec["num_colors_sum"] = int(ncol.sum())
+        rec["num_colors_max"] = int(ncol.max())
+        return rec
+    g = inp
+    rec.update(input_sha256=g.sha256(), n=g.n, nnz=g.nnz, max_degree=g.max_degree())
+    t = time.perf_counter()
+    r = oracle.rsc(g.rowptr, g.colidx)
+    rec["oracle_seconds"] = time.perf_counter() - t
+    rec["rounds"] = r.rounds
+    rec["num_colors"] = r.num_colors
+    rec["colors_sha256"] = colors_sha(r.colors)
+    rec["round_sizes"] = [int(x) for x in r.trace[:, 0]]
+    rec["sum_active"] = int(r.trace[:, 0].sum())
+    rec["sum_active_deg"] = int(r.trace[:, 1].sum())
+    rec["sum_active_lower_deg"] = int(r.trace[:, 2].sum())
+    assert oracle.check_proper(g.rowptr, g.colidx, r.colors) == 0
+    assert oracle.check_grundy(g.rowptr, g.colidx, r.colors) == 0
+    t = time.perf_counter()
+    s = oracle.seq(g.rowptr, g.colidx)
+    rec["seq_seconds"] = time.perf_counter() - t
+    rec["seq_num_colors"] = int(s.max()) + 1 if s.size else 0
+    return rec
+
+
+def main(names):
+    data = {}
+    if os.path.exists(OUT):
+        with open(OUT) as f:
+            data = json.load(f)
+    for name in names:
+        print(f"[golden] {name} ...", flush=True)
+        data[name] = one(name)
+        print(f"[golden] {name}: {json.dumps(data[name])[:300]}", flush=True)
+        with open(OUT, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:] or list(graphgen.WORKLOADS))
