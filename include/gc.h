@@ -126,21 +126,30 @@ int gc_get_stats(gc_handle h, int64_t *rounds, int32_t *num_colors);
 #define GC_TRACE_ROUNDS 65536
 int gc_get_round_sizes(gc_handle h, int64_t *sizes, int64_t cap, int64_t *rounds);
 
-/* Tunables.  None changes the result (it is a function of the graph only). */
+/* Tunables.  None changes the result (it is a function of the graph only).
+ * Read-only values are marked (get only). */
 enum gc_option {
-  GC_OPT_MODE = 1,           /* enum gc_mode, default GC_MODE_AUTO            */
-  GC_OPT_LANES = 2,          /* lanes per light vertex: 1,2,4,...,64 (def. auto) */
-  GC_OPT_HEAVY_DEGREE = 3,   /* deg > this => a whole workgroup per vertex    */
-  GC_OPT_BLOCKS_PER_CU = 4,  /* grid size of the grid-stride kernels          */
-  GC_OPT_MAX_ROUNDS = 5,     /* stop after this many rounds (debug cap; 0 = none) */
-  GC_OPT_CHUNK_ROUNDS = 6    /* rounds queued per host check in GC_MODE_CHUNKED/GRAPH */
+  GC_OPT_MODE = 1,           /* enum gc_mode, default GC_MODE_AUTO                  */
+  GC_OPT_LANES = 2,          /* lanes per light vertex, 1,2,4,..,64; 0 = auto (from
+                                the average degree)                                */
+  GC_OPT_HEAVY_DEGREE = 3,   /* deg >= this: a whole workgroup per vertex (4096)     */
+  GC_OPT_BLOCKS_PER_CU = 4,  /* workgroups per compute unit of the round kernels (8) */
+  GC_OPT_MAX_ROUNDS = 5,     /* stop after this many rounds (0 = no cap); leftover
+                                vertices make gc_get_stats return GC_EROUNDS       */
+  GC_OPT_CHUNK_ROUNDS = 6,   /* rounds queued per read-back in CHUNKED/GRAPH (8)     */
+  GC_OPT_MEDIUM_DEGREE = 7,  /* deg > this: a wavefront per vertex; 0 = auto         */
+  GC_OPT_MAX_DEGREE = 8,     /* (get only) maximum degree of the graph              */
+  GC_OPT_MEDIUM_COUNT = 9,   /* (get only) vertices on the wavefront path           */
+  GC_OPT_HEAVY_COUNT = 10,   /* (get only) vertices on the workgroup path           */
+  GC_OPT_PERSISTENT_BLOCKS_PER_CU = 11 /* workgroups per CU of the persistent kernel,
+                                1..6 (4); more are not reliably co-resident   */
 };
 enum gc_mode {
-  GC_MODE_AUTO = 0,
-  GC_MODE_HOST = 1,       /* one round per host iteration, count read back  */
-  GC_MODE_CHUNKED = 2,    /* rounds queued in chunks, empty rounds exit early */
-  GC_MODE_PERSISTENT = 3, /* one cooperative kernel, device-side round loop  */
-  GC_MODE_GRAPH = 4       /* a captured hipGraph of a chunk of rounds        */
+  GC_MODE_AUTO = 0,       /* currently PERSISTENT                                 */
+  GC_MODE_HOST = 1,       /* one round per host iteration, a flag read back       */
+  GC_MODE_CHUNKED = 2,    /* rounds queued in chunks; empty rounds exit at once   */
+  GC_MODE_PERSISTENT = 3, /* one cooperative kernel, device-side round loop      */
+  GC_MODE_GRAPH = 4       /* a captured hipGraph of a chunk of rounds            */
 };
 int gc_set_option(gc_handle h, int option, int64_t value);
 int gc_get_option(gc_handle h, int option, int64_t *value);

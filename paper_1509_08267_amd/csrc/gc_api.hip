@@ -1,0 +1,517 @@
+// gc_api.hip -- the C ABI of libgc (declared in include/gc.h): handle
+// management, argument checks, the round drivers and result read-back.
+//
+// Round drivers (GC_OPT_MODE):
+//   HOST        one speculate + detect launch pair per round, then a 4-byte
+//               read-back of "does the next round have work".
+//   CHUNKED     rounds are queued GC_OPT_CHUNK_ROUNDS at a time; a round
+//               whose set is empty returns at once, so over-queueing is
+//               harmless; one read-back per chunk.
+//   GRAPH       as CHUNKED, but the chunk is a captured hipGraph replayed
+//               with a device-side round base.
+//   PERSISTENT  one cooperative launch runs every round with grid barriers.
+// All drivers run the same phase code and give the same bits.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstddef>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "gc.h"
+#include "gc_internal.h"
+
+using gc::Ctrl;
+using gc::KArgs;
+
+namespace {
+
+thread_local std::string tl_error;
+
+struct Pinned {  // read-back area in pinned host memory
+  int32_t flag;
+  int32_t pad0;
+  int32_t counts[3];  // medium count, heavy count, max degree
+  int32_t err[2];
+  int32_t last_round;
+  int32_t ncolors;
+  int32_t abort;
+  int32_t left;
+  int32_t pad1[3];
+};
+
+}  // namespace
+
+struct gc_ctx {
+  int device = 0;
+  int cus = 0;
+  const void* rowptr = nullptr;
+  bool rp64 = false;
+  const int32_t* colidx = nullptr;
+  int64_t n = 0, m = 0;
+  uint32_t flags = 0;
+
+  Ctrl* ctrl = nullptr;       // device
+  int32_t* mlist = nullptr;   // device, n
+  int32_t* hlist = nullptr;   // device, n
+  int32_t* dcounts = nullptr; // device, 8 ints: classify counts, validate err
+  Pinned* host = nullptr;     // pinned
+  int32_t mcount = 0, hcount = 0, maxdeg = 0;
+
+  // options
+  int mode = GC_MODE_AUTO;
+  int lanes = 0;          // 0 = auto
+  int medium_min = 0;     // 0 = auto (deg > medium threshold -> medium)
+  int heavy_min = 4096;   // deg >= heavy_min -> heavy
+  int blocks_per_cu = 8;
+  int persist_per_cu = 4;  // co-resident workgroups per CU of the persistent kernel
+  int max_rounds = 0;
+  int chunk_rounds = 8;
+  bool lists_dirty = false;
+
+  // last colouring
+  hipEvent_t done = nullptr;
+  bool in_flight = false;
+  bool stats_ready = false;
+
+  // captured chunk (GRAPH mode)
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  int32_t* g_st = nullptr;
+  int g_chunk = 0, g_lanes = 0, g_light = 0;
+
+  std::string err;
+};
+
+static int set_err(gc_ctx* h, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+static int set_err(gc_ctx* h, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  tl_error = buf;
+  if (h) h->err = buf;
+  return code;
+}
+
+#define HIPCHECK(h, expr)                                                             \
+  do {                                                                                \
+    hipError_t e_ = (hipError_t)(expr);                                               \
+    if (e_ != hipSuccess)                                                             \
+      return set_err(h, GC_EDEVICE, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_),   \
+                     __FILE__, __LINE__);                                             \
+  } while (0)
+
+static int auto_lanes(const gc_ctx* h) {
+  if (h->lanes) return h->lanes;
+  double avg = h->n ? (double)h->m / (double)h->n : 0.0;
+  int L = 1;
+  while (L < 32 && L * 2 <= avg) L *= 2;  // about two entries per lane
+  return std::max(L, 2);
+}
+
+static int light_max_of(const gc_ctx* h, int L) {
+  if (h->medium_min > 0) return h->medium_min;
+  return std::max(8 * L, 64);
+}
+
+static KArgs make_args(const gc_ctx* h, int32_t* st, int light_max) {
+  KArgs a{};
+  a.rowptr = h->rowptr;
+  a.colidx = h->colidx;
+  a.st = st;
+  a.n = (int32_t)h->n;
+  a.light_max = light_max;
+  a.mlist = h->mlist;
+  a.mcount = h->mcount;
+  a.hlist = h->hlist;
+  a.hcount = h->hcount;
+  a.ctrl = h->ctrl;
+  return a;
+}
+
+static int grid_of(const gc_ctx* h) { return std::max(1, h->cus * h->blocks_per_cu); }
+
+// Build the medium and heavy lists for the current thresholds; synchronous.
+static int classify(gc_ctx* h, hipStream_t s) {
+  const int L = auto_lanes(h);
+  const int light = light_max_of(h, L);
+  const int heavy = std::max(h->heavy_min, light + 1);
+  HIPCHECK(h, hipMemsetAsync(h->dcounts, 0, 3 * sizeof(int32_t), s));
+  int rc = gc::launch_classify(h->rowptr, h->rp64, (int32_t)h->n, light, heavy, h->mlist, h->hlist,
+                               h->dcounts, grid_of(h), s);
+  if (rc) return set_err(h, GC_EDEVICE, "classify launch: %s", hipGetErrorString((hipError_t)rc));
+  HIPCHECK(h, hipMemcpyAsync(h->host->counts, h->dcounts, 3 * sizeof(int32_t),
+                             hipMemcpyDeviceToHost, s));
+  HIPCHECK(h, hipStreamSynchronize(s));
+  h->mcount = h->host->counts[0];
+  h->hcount = h->host->counts[1];
+  h->maxdeg = h->host->counts[2];
+  h->lists_dirty = false;
+  return GC_OK;
+}
+
+static void free_graph(gc_ctx* h) {
+  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  h->gexec = nullptr;
+  h->graph = nullptr;
+  h->g_st = nullptr;
+}
+
+static void free_ctx(gc_ctx* h) {
+  if (!h) return;
+  free_graph(h);
+  if (h->done) (void)hipEventDestroy(h->done);
+  if (h->ctrl) (void)hipFree(h->ctrl);
+  if (h->mlist) (void)hipFree(h->mlist);
+  if (h->hlist) (void)hipFree(h->hlist);
+  if (h->dcounts) (void)hipFree(h->dcounts);
+  if (h->host) (void)hipHostFree(h->host);
+  delete h;
+}
+
+extern "C" int gc_create(gc_handle* out, const void* rowptr, const int32_t* colidx, int64_t n,
+                         int64_t m, uint32_t flags, void* stream) {
+  if (!out) return set_err(nullptr, GC_EINVAL, "gc_create: out is NULL");
+  *out = nullptr;
+  if (n < 0 || m < 0) return set_err(nullptr, GC_EINVAL, "gc_create: negative n or m");
+  if (n >= INT32_MAX) return set_err(nullptr, GC_ETOOBIG, "gc_create: n must be below 2^31 - 1");
+  if (!(flags & GC_ROWPTR_I64) && m > INT32_MAX)
+    return set_err(nullptr, GC_ETOOBIG, "gc_create: m > 2^31 - 1 needs GC_ROWPTR_I64");
+  if (flags & ~(uint32_t)(GC_ROWPTR_I64 | GC_VALIDATE | GC_ROWS_SORTED))
+    return set_err(nullptr, GC_EINVAL, "gc_create: unknown flag bits 0x%x", flags);
+  if (!rowptr) return set_err(nullptr, GC_EINVAL, "gc_create: rowptr is NULL");
+  if (m > 0 && !colidx) return set_err(nullptr, GC_EINVAL, "gc_create: colidx is NULL");
+
+  gc_ctx* h = new (std::nothrow) gc_ctx();
+  if (!h) return set_err(nullptr, GC_ENOMEM, "gc_create: out of host memory");
+  h->rowptr = rowptr;
+  h->rp64 = (flags & GC_ROWPTR_I64) != 0;
+  h->colidx = colidx;
+  h->n = n;
+  h->m = m;
+  h->flags = flags;
+  hipStream_t s = (hipStream_t)stream;
+
+#define CREATE_CHECK(expr)                                                                      \
+  do {                                                                                          \
+    hipError_t e_ = (hipError_t)(expr);                                                         \
+    if (e_ != hipSuccess) {                                                                     \
+      int code_ = (e_ == hipErrorOutOfMemory || e_ == hipErrorMemoryAllocation) ? GC_ENOMEM      \
+                                                                                : GC_EDEVICE;   \
+      set_err(nullptr, code_, "gc_create: %s: %s", #expr, hipGetErrorString(e_));               \
+      free_ctx(h);                                                                              \
+      return code_;                                                                             \
+    }                                                                                           \
+  } while (0)
+
+  CREATE_CHECK(hipGetDevice(&h->device));
+  CREATE_CHECK(hipDeviceGetAttribute(&h->cus, hipDeviceAttributeMultiprocessorCount, h->device));
+  CREATE_CHECK(hipMalloc((void**)&h->ctrl, sizeof(Ctrl)));
+  CREATE_CHECK(hipMalloc((void**)&h->mlist, (size_t)std::max<int64_t>(n, 1) * sizeof(int32_t)));
+  CREATE_CHECK(hipMalloc((void**)&h->hlist, (size_t)std::max<int64_t>(n, 1) * sizeof(int32_t)));
+  CREATE_CHECK(hipMalloc((void**)&h->dcounts, 8 * sizeof(int32_t)));
+  CREATE_CHECK(hipHostMalloc((void**)&h->host, sizeof(Pinned), hipHostMallocDefault));
+  CREATE_CHECK(hipEventCreateWithFlags(&h->done, hipEventDisableTiming));
+  memset(h->host, 0, sizeof(Pinned));
+
+  if (flags & GC_VALIDATE) {
+    int32_t init_err[2] = {INT32_MAX, -1};
+    CREATE_CHECK(hipMemcpyAsync(h->dcounts + 4, init_err, sizeof init_err, hipMemcpyHostToDevice, s));
+    CREATE_CHECK(gc::launch_validate(rowptr, h->rp64, colidx, (int32_t)n, m,
+                                     (flags & GC_ROWS_SORTED) != 0, h->dcounts + 4, grid_of(h), s));
+    CREATE_CHECK(hipMemcpyAsync(h->host->err, h->dcounts + 4, sizeof init_err,
+                                hipMemcpyDeviceToHost, s));
+    CREATE_CHECK(hipStreamSynchronize(s));
+    int code = h->host->err[0];
+    if (code != INT32_MAX) {
+      static const char* what[] = {"",
+                                   "rowptr[0] != 0 or rowptr[n] != m",
+                                   "rowptr decreases or leaves [0, m]",
+                                   "neighbour id out of range",
+                                   "self-loop (a simple graph has none)",
+                                   "duplicate entry in a row",
+                                   "row not ascending although GC_ROWS_SORTED was given",
+                                   "edge stored in one direction only (CSR not symmetric)"};
+      set_err(nullptr, GC_EINVAL, "gc_create: invalid graph: %s (vertex %d)",
+              (code >= 1 && code <= 7) ? what[code] : "?", h->host->err[1]);
+      free_ctx(h);
+      return GC_EINVAL;
+    }
+  }
+  int rc = classify(h, s);
+  if (rc) {
+    tl_error = h->err;
+    free_ctx(h);
+    return rc;
+  }
+  *out = h;
+  return GC_OK;
+}
+
+static int ensure_idle(gc_ctx* h) {
+  if (!h->in_flight) return GC_OK;
+  hipError_t q = hipEventQuery(h->done);
+  if (q == hipErrorNotReady) return set_err(h, GC_EBUSY, "handle busy: previous gc_color not finished");
+  if (q != hipSuccess) return set_err(h, GC_EDEVICE, "previous call failed: %s", hipGetErrorString(q));
+  h->in_flight = false;
+  return GC_OK;
+}
+
+static int resolve_mode(const gc_ctx* h) {
+  int mode = h->mode == GC_MODE_AUTO ? GC_MODE_PERSISTENT : h->mode;
+  // a captured chunk cannot stop inside itself: honour a round cap by queueing
+  if (mode == GC_MODE_GRAPH && h->max_rounds > 0) mode = GC_MODE_CHUNKED;
+  return mode;
+}
+
+static int capture_chunk(gc_ctx* h, const KArgs& a, int L, int K) {
+  free_graph(h);
+  hipStream_t cs;
+  HIPCHECK(h, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    (void)hipStreamDestroy(cs);
+    return set_err(h, GC_EDEVICE, "begin capture: %s", hipGetErrorString(e));
+  }
+  int rc = 0;
+  const bool sorted = (h->flags & GC_ROWS_SORTED) != 0;
+  for (int j = 0; j < K && !rc; ++j) {
+    rc = gc::launch_round(a, h->rp64, sorted, L, 0, j, true, grid_of(h), cs);
+    if (!rc) rc = gc::launch_round(a, h->rp64, sorted, L, 1, j, true, grid_of(h), cs);
+  }
+  if (!rc) rc = gc::launch_advance_base(a, K, cs);
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(cs, &g);
+  (void)hipStreamDestroy(cs);
+  if (rc || e2 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return set_err(h, GC_EDEVICE, "capture failed: %s",
+                   hipGetErrorString(rc ? (hipError_t)rc : e2));
+  }
+  hipGraphExec_t x = nullptr;
+  e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return set_err(h, GC_EDEVICE, "instantiate: %s", hipGetErrorString(e));
+  }
+  h->graph = g;
+  h->gexec = x;
+  h->g_st = a.st;
+  h->g_chunk = K;
+  h->g_lanes = L;
+  h->g_light = a.light_max;
+  return GC_OK;
+}
+
+extern "C" int gc_color(gc_handle h, int32_t* colors_out, void* stream) {
+  if (!h) return set_err(nullptr, GC_EINVAL, "gc_color: NULL handle");
+  if (h->n > 0 && !colors_out) return set_err(h, GC_EINVAL, "gc_color: colors_out is NULL");
+  int rc = ensure_idle(h);
+  if (rc) return rc;
+  int cur = 0;
+  HIPCHECK(h, hipGetDevice(&cur));
+  if (cur != h->device) HIPCHECK(h, hipSetDevice(h->device));
+  hipStream_t s = (hipStream_t)stream;
+  if (h->lists_dirty) {
+    rc = classify(h, s);
+    if (rc) return rc;
+  }
+  h->stats_ready = false;
+  const int L = auto_lanes(h);
+  const int light = light_max_of(h, L);
+  const KArgs a = make_args(h, colors_out, light);
+  const bool sorted = (h->flags & GC_ROWS_SORTED) != 0;
+  const int grid = grid_of(h);
+  const int mode = resolve_mode(h);
+
+#define LCHECK(expr)                                                                      \
+  do {                                                                                    \
+    int r_ = (expr);                                                                      \
+    if (r_) return set_err(h, GC_EDEVICE, "%s: %s", #expr, hipGetErrorString((hipError_t)r_)); \
+  } while (0)
+
+  LCHECK(gc::launch_init(a, s, std::min(grid, 1024)));
+  if (mode == GC_MODE_PERSISTENT) {
+    int maxg = 0;
+    LCHECK(gc::persistent_max_grid(h->rp64, sorted, L, &maxg));
+    // The occupancy query admits more workgroups per CU than are co-resident in
+    // practice (a barrier with 7-8 per CU never completes on MI355X), so the
+    // grid is capped at persist_per_cu per CU, which has been verified.
+    int pg = std::min(maxg, h->cus * h->persist_per_cu);
+    if (pg < 1) return set_err(h, GC_EDEVICE, "persistent kernel cannot be resident");
+    LCHECK(gc::launch_persistent(a, h->rp64, sorted, L, h->max_rounds, pg, s));
+  } else {
+    LCHECK(gc::launch_round(a, h->rp64, sorted, L, 1, 1, false, grid, s));  // round 1
+    int r = 1;  // last round queued
+    const int K = std::max(1, h->chunk_rounds);
+    for (;;) {
+      HIPCHECK(h, hipMemcpyAsync(&h->host->flag, &h->ctrl->more[(r + 1) % 3].v, sizeof(int32_t),
+                                 hipMemcpyDeviceToHost, s));
+      HIPCHECK(h, hipStreamSynchronize(s));
+      if (!h->host->flag) break;
+      if (h->max_rounds > 0 && r >= h->max_rounds) break;
+      if (mode == GC_MODE_HOST) {
+        ++r;
+        LCHECK(gc::launch_round(a, h->rp64, sorted, L, 0, r, false, grid, s));
+        LCHECK(gc::launch_round(a, h->rp64, sorted, L, 1, r, false, grid, s));
+      } else if (mode == GC_MODE_CHUNKED) {
+        int upto = r + K;
+        if (h->max_rounds > 0) upto = std::min(upto, h->max_rounds);
+        for (int q = r + 1; q <= upto; ++q) {
+          LCHECK(gc::launch_round(a, h->rp64, sorted, L, 0, q, false, grid, s));
+          LCHECK(gc::launch_round(a, h->rp64, sorted, L, 1, q, false, grid, s));
+        }
+        r = upto;
+      } else if (mode == GC_MODE_GRAPH) {
+        if (!h->gexec || h->g_st != colors_out || h->g_chunk != K || h->g_lanes != L ||
+            h->g_light != light) {
+          rc = capture_chunk(h, a, L, K);
+          if (rc) return rc;
+        }
+        HIPCHECK(h, hipGraphLaunch(h->gexec, s));
+        r += K;  // the chunk ran rounds r+1 .. r+K (round_base advanced by K)
+      } else {
+        return set_err(h, GC_EINVAL, "unknown mode %d", mode);
+      }
+    }
+  }
+  LCHECK(gc::launch_finish(a, std::min(grid, 512), s));
+  static_assert(offsetof(Pinned, ncolors) == offsetof(Pinned, last_round) + 4, "layout");
+  HIPCHECK(h, hipMemcpyAsync(&h->host->last_round, &h->ctrl->last_round.v, 4, hipMemcpyDeviceToHost, s));
+  HIPCHECK(h, hipMemcpyAsync(&h->host->ncolors, &h->ctrl->ncolors.v, 4, hipMemcpyDeviceToHost, s));
+  HIPCHECK(h, hipMemcpyAsync(&h->host->abort, &h->ctrl->abort.v, 4, hipMemcpyDeviceToHost, s));
+  HIPCHECK(h, hipMemcpyAsync(&h->host->left, &h->ctrl->left.v, 4, hipMemcpyDeviceToHost, s));
+  HIPCHECK(h, hipEventRecord(h->done, s));
+  h->in_flight = true;
+  h->stats_ready = true;
+  return GC_OK;
+}
+
+static int wait_done(gc_ctx* h) {
+  if (!h->stats_ready) return set_err(h, GC_EINVAL, "no colouring has been run on this handle");
+  if (h->in_flight) {
+    HIPCHECK(h, hipEventSynchronize(h->done));
+    h->in_flight = false;
+  }
+  if (h->host->abort) return set_err(h, GC_EDEVICE, "persistent kernel: grid barrier timed out");
+  if (h->host->left) return set_err(h, GC_EROUNDS, "round cap reached with %d vertices uncoloured",
+                                    h->host->left);
+  return GC_OK;
+}
+
+extern "C" int gc_get_stats(gc_handle h, int64_t* rounds, int32_t* num_colors) {
+  if (!h) return set_err(nullptr, GC_EINVAL, "gc_get_stats: NULL handle");
+  int rc = wait_done(h);
+  if (rounds) *rounds = h->host->last_round;
+  if (num_colors) *num_colors = h->host->ncolors;
+  return rc;
+}
+
+extern "C" int gc_get_round_sizes(gc_handle h, int64_t* sizes, int64_t cap, int64_t* rounds) {
+  if (!h) return set_err(nullptr, GC_EINVAL, "gc_get_round_sizes: NULL handle");
+  if (cap < 0 || (cap > 0 && !sizes)) return set_err(h, GC_EINVAL, "gc_get_round_sizes: bad buffer");
+  int rc = wait_done(h);
+  if (rc && rc != GC_EROUNDS) return rc;
+  int64_t R = h->host->last_round;
+  if (rounds) *rounds = R;
+  int64_t k = std::min<int64_t>(std::min<int64_t>(R, cap), gc::kTraceRounds);
+  if (k > 0) {
+    int32_t* tmp = new (std::nothrow) int32_t[k];
+    if (!tmp) return set_err(h, GC_ENOMEM, "gc_get_round_sizes: host memory");
+    hipError_t e = hipMemcpy(tmp, h->ctrl->trace, k * sizeof(int32_t), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+      delete[] tmp;
+      return set_err(h, GC_EDEVICE, "trace read-back: %s", hipGetErrorString(e));
+    }
+    for (int64_t i = 0; i < k; ++i) sizes[i] = tmp[i];
+    delete[] tmp;
+  }
+  return rc;
+}
+
+extern "C" int gc_set_option(gc_handle h, int option, int64_t value) {
+  if (!h) return set_err(nullptr, GC_EINVAL, "gc_set_option: NULL handle");
+  int rc = ensure_idle(h);
+  if (rc) return rc;
+  switch (option) {
+    case GC_OPT_MODE:
+      if (value < GC_MODE_AUTO || value > GC_MODE_GRAPH) break;
+      h->mode = (int)value;
+      return GC_OK;
+    case GC_OPT_LANES:
+      if (value != 0 && (value < 1 || value > 64 || (value & (value - 1)))) break;
+      h->lanes = (int)value;
+      h->lists_dirty = true;
+      return GC_OK;
+    case GC_OPT_MEDIUM_DEGREE:
+      if (value < 0 || value > INT32_MAX - 1) break;
+      h->medium_min = (int)value;
+      h->lists_dirty = true;
+      return GC_OK;
+    case GC_OPT_HEAVY_DEGREE:
+      if (value < 1 || value > INT32_MAX) break;
+      h->heavy_min = (int)value;
+      h->lists_dirty = true;
+      return GC_OK;
+    case GC_OPT_BLOCKS_PER_CU:
+      if (value < 1 || value > 64) break;
+      h->blocks_per_cu = (int)value;
+      return GC_OK;
+    case GC_OPT_MAX_ROUNDS:
+      if (value < 0 || value > INT32_MAX) break;
+      h->max_rounds = (int)value;
+      return GC_OK;
+    case GC_OPT_CHUNK_ROUNDS:
+      if (value < 1 || value > 1024) break;
+      h->chunk_rounds = (int)value;
+      return GC_OK;
+    case GC_OPT_PERSISTENT_BLOCKS_PER_CU:
+      if (value < 1 || value > 6) break;
+      h->persist_per_cu = (int)value;
+      return GC_OK;
+    default:
+      return set_err(h, GC_EINVAL, "gc_set_option: unknown option %d", option);
+  }
+  return set_err(h, GC_EINVAL, "gc_set_option: value %lld out of range for option %d",
+                 (long long)value, option);
+}
+
+extern "C" int gc_get_option(gc_handle h, int option, int64_t* value) {
+  if (!h || !value) return set_err(h, GC_EINVAL, "gc_get_option: NULL argument");
+  switch (option) {
+    case GC_OPT_MODE: *value = resolve_mode(h); return GC_OK;
+    case GC_OPT_LANES: *value = auto_lanes(h); return GC_OK;
+    case GC_OPT_MEDIUM_DEGREE: *value = light_max_of(h, auto_lanes(h)); return GC_OK;
+    case GC_OPT_HEAVY_DEGREE: *value = h->heavy_min; return GC_OK;
+    case GC_OPT_BLOCKS_PER_CU: *value = h->blocks_per_cu; return GC_OK;
+    case GC_OPT_MAX_ROUNDS: *value = h->max_rounds; return GC_OK;
+    case GC_OPT_CHUNK_ROUNDS: *value = h->chunk_rounds; return GC_OK;
+    case GC_OPT_PERSISTENT_BLOCKS_PER_CU: *value = h->persist_per_cu; return GC_OK;
+    case GC_OPT_MAX_DEGREE: *value = h->maxdeg; return GC_OK;
+    case GC_OPT_MEDIUM_COUNT: *value = h->mcount; return GC_OK;
+    case GC_OPT_HEAVY_COUNT: *value = h->hcount; return GC_OK;
+    default: return set_err(h, GC_EINVAL, "gc_get_option: unknown option %d", option);
+  }
+}
+
+extern "C" int gc_destroy(gc_handle h) {
+  if (!h) return GC_OK;
+  int rc = GC_OK;
+  if (h->in_flight) {
+    hipError_t e = hipEventSynchronize(h->done);
+    if (e != hipSuccess) rc = set_err(nullptr, GC_EDEVICE, "gc_destroy: %s", hipGetErrorString(e));
+  }
+  free_ctx(h);
+  return rc;
+}
+
+extern "C" const char* gc_last_error(gc_handle h) {
+  return h ? h->err.c_str() : tl_error.c_str();
+}
+
+extern "C" const char* gc_version(void) { return "0.1.0"; }

@@ -1,0 +1,71 @@
+// gc_internal.h -- shared between the C-ABI engine and the gfx950 kernels.
+//
+// State encoding (one int32 per vertex, the caller's colour array):
+//   s >= 0   the vertex's colour is final (= s)
+//   s <  0   the vertex is still being coloured; its tentative colour of the
+//            current round is ~s (so the initial -1 means "tentative 0")
+// A round's speculate phase rewrites only negative entries (negative stays
+// negative), and its detect phase turns a winner's ~t into t.  A reader that
+// decodes (s < 0 ? ~s : s) therefore sees the same tentative colour before and
+// after a concurrent commit, which is what lets detect and commit share one
+// pass.
+#pragma once
+#include <cstdint>
+
+namespace gc {
+
+constexpr int kWave = 64;           // CDNA wavefront width
+constexpr int kBlock = 256;         // threads per workgroup of the round kernels
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kTraceRounds = 65536; // rounds whose |U_r| is recorded
+constexpr int kHeavyWindow = 4096;  // LDS colour window of the block-per-vertex path (bits)
+
+// One 128-byte line per field group that different blocks write, so that
+// flags and counters never share a line.
+struct alignas(128) Line {
+  int32_t v;
+  int32_t pad[31];
+};
+
+struct Ctrl {
+  Line more[3];          // slot r % 3 == 1 when round r has uncoloured vertices
+  Line last_round;       // last round that had uncoloured vertices
+  Line round_base;       // first round of the next captured chunk
+  Line ncolors;          // max colour + 1
+  Line bar;              // grid barrier arrivals (monotonic)
+  Line abort;            // set when a barrier wait exceeded its spin limit
+  Line left;             // vertices still uncoloured at the round cap
+  int32_t trace[kTraceRounds];  // |U_r| at slot r - 1
+};
+
+// Arguments of every round kernel.
+struct KArgs {
+  const void* rowptr;     // int32 or int64, n + 1
+  const int32_t* colidx;  // nnz
+  int32_t* st;            // n, the state / output colours
+  int32_t n;
+  int32_t light_max;      // deg <= light_max: a group of L lanes per vertex
+  const int32_t* mlist;   // medium vertices (light_max < deg <= heavy_min - 1): a wavefront each
+  int32_t mcount;
+  const int32_t* hlist;   // heavy vertices: a whole workgroup each
+  int32_t hcount;
+  Ctrl* ctrl;
+};
+
+// Launch helpers implemented in gc_kernels.hip.  All return a hipError_t
+// cast to int.
+int launch_init(const KArgs& a, void* stream, int grid);
+int launch_round(const KArgs& a, bool rp64, bool sorted, int lanes, int phase /*0 spec, 1 detect*/,
+                 int round, bool round_from_base, int grid, void* stream);
+int launch_advance_base(const KArgs& a, int by, void* stream);
+int launch_finish(const KArgs& a, int grid, void* stream);
+int launch_persistent(const KArgs& a, bool rp64, bool sorted, int lanes, int max_rounds,
+                      int grid, void* stream);
+int persistent_max_grid(bool rp64, bool sorted, int lanes, int* grid_out);
+int launch_classify(const void* rowptr, bool rp64, int32_t n, int32_t light_max, int32_t heavy_min,
+                    int32_t* mlist, int32_t* hlist, int32_t* counts /*[3]: medium, heavy, maxdeg*/,
+                    int grid, void* stream);
+int launch_validate(const void* rowptr, bool rp64, const int32_t* colidx, int32_t n, int64_t m,
+                    bool sorted, int32_t* err /*[2]: code, where*/, int grid, void* stream);
+
+}  // namespace gc

@@ -1,0 +1,680 @@
+// gc_kernels.hip -- gfx950 kernels of round-synchronous speculative colouring.
+//
+// One round (Algorithm 1 of Section 3.1 with every vertex its own block):
+//   speculate  each uncoloured vertex v takes the least colour that is not
+//              final on any neighbour (First Fit, Section 3);
+//   detect     v loses when a lower-id neighbour also coloured this round
+//              took the same colour; otherwise v's colour becomes final.
+// Round 1 needs no speculate pass: nothing is final yet, so every vertex
+// tries colour 0, which the initial state -1 (= ~0) already encodes.
+//
+// Work mapping (wave64):
+//   light  deg <= light_max: a group of L lanes per vertex (L = 1..64).
+//          Each wavefront walks 64 consecutive vertex ids at a time, ballots
+//          the uncoloured light ones and hands them to its 64/L groups in
+//          ascending order (an in-wave prefix sum over the ballot), so rows
+//          are read in address order and no global worklist or append
+//          atomics exist.
+//   medium light_max < deg < heavy threshold: one wavefront per vertex,
+//          from a static list built once per graph.
+//   heavy  one 256-thread workgroup per vertex, from a static list; its
+//          forbidden-colour window is a bitmask in LDS.
+// The forbidden colours of a light or medium vertex are a 64-bit register
+// mask per lane, OR-reduced across the group with cross-lane shuffles; the
+// pick is find-first-zero.  Colours beyond the first 64 (or 4096 for heavy
+// vertices) are handled by sliding the window, which only happens when a
+// vertex sees that many distinct final colours.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstdint>
+
+#include "gc_internal.h"
+
+namespace gc {
+
+enum { kSpec = 0, kDetect = 1 };
+
+// ------------------------------------------------------------ helpers --
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t x, int mask) {
+  int lo = __shfl_xor((int)(uint32_t)x, mask);
+  int hi = __shfl_xor((int)(uint32_t)(x >> 32), mask);
+  return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+template <typename T>
+__device__ __forceinline__ T shfl_any(T x, int src);
+template <>
+__device__ __forceinline__ int32_t shfl_any<int32_t>(int32_t x, int src) {
+  return __shfl(x, src);
+}
+template <>
+__device__ __forceinline__ int64_t shfl_any<int64_t>(int64_t x, int src) {
+  int lo = __shfl((int)(uint32_t)x, src);
+  int hi = __shfl((int)(uint32_t)((uint64_t)x >> 32), src);
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+template <int L>
+__device__ __forceinline__ uint64_t group_or(uint64_t m) {
+#pragma unroll
+  for (int off = L / 2; off > 0; off >>= 1) m |= shfl_xor64(m, off);
+  return m;
+}
+
+// position of the k-th (0-based) set bit of m; k < popcount(m)
+__device__ __forceinline__ int nth_set_bit(uint64_t m, int k) {
+  int pos = 0;
+#pragma unroll
+  for (int w = 32; w > 0; w >>= 1) {
+    int c = __popcll((m >> pos) & ((1ull << w) - 1));
+    if (k >= c) {
+      k -= c;
+      pos += w;
+    }
+  }
+  return pos;
+}
+
+// tentative colour carried by a state word (final colours decode to themselves)
+__device__ __forceinline__ int tent_of(int s) { return s < 0 ? ~s : s; }
+
+// ------------------------------------------- per-vertex work, L lanes --
+
+// Least colour not final on any neighbour of the row [b, e), computed by a
+// group of L lanes (gl = lane in group).  Every lane returns the result.
+template <typename RP, int L>
+__device__ __forceinline__ int spec_group(const int32_t* __restrict__ colidx,
+                                          const int32_t* __restrict__ st, RP b, RP e,
+                                          int gl) {
+  int base = 0;
+  for (;;) {
+    uint64_t m = 0;
+    RP k = b + gl;
+    for (; k + L < e; k += 2 * L) {  // two gathers in flight per lane
+      int u0 = colidx[k];
+      int u1 = colidx[k + L];
+      int c0 = st[u0];
+      int c1 = st[u1];
+      unsigned r0 = (unsigned)c0 - (unsigned)base;
+      unsigned r1 = (unsigned)c1 - (unsigned)base;
+      if (c0 >= 0 && r0 < 64u) m |= 1ull << r0;
+      if (c1 >= 0 && r1 < 64u) m |= 1ull << r1;
+    }
+    if (k < e) {
+      int c0 = st[colidx[k]];
+      unsigned r0 = (unsigned)c0 - (unsigned)base;
+      if (c0 >= 0 && r0 < 64u) m |= 1ull << r0;
+    }
+    m = group_or<L>(m);
+    if (m != ~0ull) return base + __builtin_ctzll(~m);
+    base += 64;  // all of base..base+63 are taken: slide the window
+  }
+}
+
+// Does a lower-id neighbour of v carry tentative colour t?  Group of L lanes.
+// With sorted rows the scan stops at the first neighbour id >= v.
+template <typename RP, int L, bool SORTED>
+__device__ __forceinline__ bool detect_group(const int32_t* __restrict__ colidx,
+                                             const int32_t* __restrict__ st, RP b, RP e,
+                                             int v, int t, int gl, uint64_t gmask) {
+  for (RP kb = b; kb < e; kb += L) {
+    RP k = kb + gl;
+    bool conf = false, past = false;
+    if (k < e) {
+      int u = colidx[k];
+      if (u < v) {
+        conf = tent_of(st[u]) == t;
+      } else {
+        past = true;
+      }
+    } else {
+      past = true;
+    }
+    if (__ballot(conf) & gmask) return true;
+    if (SORTED && (__ballot(past) & gmask)) return false;
+  }
+  return false;
+}
+
+// ------------------------------------------------ per-vertex, workgroup --
+
+struct HeavySmem {
+  uint32_t bm[kHeavyWindow / 32];
+  int first;
+  int active;  // per-block tallies of a detect phase
+  int lost;
+};
+
+template <typename RP>
+__device__ int spec_block(const int32_t* __restrict__ colidx, const int32_t* __restrict__ st,
+                          RP b, RP e, HeavySmem& sm) {
+  const int tid = threadIdx.x;
+  int base = 0;
+  for (;;) {
+    for (int w = tid; w < kHeavyWindow / 32; w += kBlock) sm.bm[w] = 0;
+    if (tid == 0) sm.first = INT_MAX;
+    __syncthreads();
+    uint64_t m = 0;
+    RP k = b + tid;
+    for (; k + kBlock < e; k += 2 * kBlock) {
+      int c0 = st[colidx[k]];
+      int c1 = st[colidx[k + kBlock]];
+      unsigned r0 = (unsigned)c0 - (unsigned)base;
+      unsigned r1 = (unsigned)c1 - (unsigned)base;
+      if (c0 >= 0) {
+        if (r0 < 64u) m |= 1ull << r0;
+        else if (r0 < (unsigned)kHeavyWindow) atomicOr(&sm.bm[r0 >> 5], 1u << (r0 & 31));
+      }
+      if (c1 >= 0) {
+        if (r1 < 64u) m |= 1ull << r1;
+        else if (r1 < (unsigned)kHeavyWindow) atomicOr(&sm.bm[r1 >> 5], 1u << (r1 & 31));
+      }
+    }
+    if (k < e) {
+      int c0 = st[colidx[k]];
+      unsigned r0 = (unsigned)c0 - (unsigned)base;
+      if (c0 >= 0) {
+        if (r0 < 64u) m |= 1ull << r0;
+        else if (r0 < (unsigned)kHeavyWindow) atomicOr(&sm.bm[r0 >> 5], 1u << (r0 & 31));
+      }
+    }
+    m = group_or<kWave>(m);
+    if (lane_id() == 0) {
+      atomicOr(&sm.bm[0], (uint32_t)m);
+      atomicOr(&sm.bm[1], (uint32_t)(m >> 32));
+    }
+    __syncthreads();
+    for (int w = tid; w < kHeavyWindow / 32; w += kBlock) {
+      uint32_t x = sm.bm[w];
+      if (x != ~0u) atomicMin(&sm.first, w * 32 + __builtin_ctz(~x));
+    }
+    __syncthreads();
+    int f = sm.first;
+    __syncthreads();  // everyone has read first/bm before they are reused
+    if (f != INT_MAX) return base + f;
+    base += kHeavyWindow;
+  }
+}
+
+template <typename RP, bool SORTED>
+__device__ bool detect_block(const int32_t* __restrict__ colidx, const int32_t* __restrict__ st,
+                             RP b, RP e, int v, int t) {
+  const int tid = threadIdx.x;
+  for (RP kb = b; kb < e; kb += kBlock) {
+    RP k = kb + tid;
+    int conf = 0, past = 0;
+    if (k < e) {
+      int u = colidx[k];
+      if (u < v) conf = tent_of(st[u]) == t;
+      else past = 1;
+    } else {
+      past = 1;
+    }
+    if (__syncthreads_or(conf)) return true;
+    if (SORTED && __syncthreads_or(past)) return false;
+  }
+  return false;
+}
+
+// ---------------------------------------------------------- one phase --
+
+// Per-thread tallies of a phase, reduced per block at the end.
+struct Tally {
+  int active;  // uncoloured vertices this thread's group/wave/block led
+  int lost;    // of which lost (detect only)
+};
+
+template <typename RP, int L, int PHASE, bool SORTED>
+__device__ void light_phase(const KArgs& a, long wave_gid, long nwaves, Tally& tl) {
+  const int lane = lane_id();
+  const int gl = lane & (L - 1);
+  const int grp = lane / L;
+  constexpr int G = kWave / L;
+  const uint64_t gmask = (L == kWave) ? ~0ull : (((1ull << L) - 1) << (grp * L));
+  const RP* __restrict__ rp = (const RP*)a.rowptr;
+  const long nchunks = ((long)a.n + kWave - 1) / kWave;
+  for (long ch = wave_gid; ch < nchunks; ch += nwaves) {
+    const int v = (int)(ch * kWave) + lane;
+    bool act = false;
+    int s = 0;
+    RP b = 0, e = 0;
+    if (v < a.n) {
+      s = a.st[v];
+      if (s < 0) {
+        b = rp[v];
+        e = rp[v + 1];
+        act = (e - b) <= (RP)a.light_max;
+      }
+    }
+    const uint64_t am = __ballot(act);
+    if (am == 0) continue;
+    const int cnt = __popcll(am);
+    for (int p = 0; p < cnt; p += G) {  // wave-uniform
+      const int k = p + grp;
+      const bool valid = k < cnt;
+      const int pos = nth_set_bit(am, valid ? k : 0);
+      const RP vb = shfl_any<RP>(b, pos);
+      const RP ve = shfl_any<RP>(e, pos);
+      const int vs = shfl_any<int32_t>(s, pos);
+      const int vv = (int)(ch * kWave) + pos;
+      if (valid) {  // group-uniform
+        if (PHASE == kSpec) {
+          int t = spec_group<RP, L>(a.colidx, a.st, vb, ve, gl);
+          if (gl == 0) a.st[vv] = ~t;
+        } else {
+          const int t = ~vs;
+          bool lose = detect_group<RP, L, SORTED>(a.colidx, a.st, vb, ve, vv, t, gl, gmask);
+          if (gl == 0) {
+            if (!lose) a.st[vv] = t;
+            tl.lost += lose;
+          }
+        }
+        if (gl == 0) tl.active += 1;
+      }
+    }
+  }
+}
+
+template <typename RP, int PHASE, bool SORTED>
+__device__ void medium_phase(const KArgs& a, long wave_gid, long nwaves, Tally& tl) {
+  const int lane = lane_id();
+  const RP* __restrict__ rp = (const RP*)a.rowptr;
+  for (long i = wave_gid; i < a.mcount; i += nwaves) {
+    const int v = a.mlist[i];
+    const int s = a.st[v];
+    if (s >= 0) continue;  // wave-uniform
+    const RP b = rp[v], e = rp[v + 1];
+    if (PHASE == kSpec) {
+      int t = spec_group<RP, kWave>(a.colidx, a.st, b, e, lane);
+      if (lane == 0) a.st[v] = ~t;
+    } else {
+      const int t = ~s;
+      bool lose = detect_group<RP, kWave, SORTED>(a.colidx, a.st, b, e, v, t, lane, ~0ull);
+      if (lane == 0) {
+        if (!lose) a.st[v] = t;
+        tl.lost += lose;
+      }
+    }
+    if (lane == 0) tl.active += 1;
+  }
+}
+
+template <typename RP, int PHASE, bool SORTED>
+__device__ void heavy_phase(const KArgs& a, long blk, long nblk, Tally& tl, HeavySmem& sm) {
+  const RP* __restrict__ rp = (const RP*)a.rowptr;
+  for (long i = blk; i < a.hcount; i += nblk) {
+    const int v = a.hlist[i];
+    const int s = a.st[v];
+    __syncthreads();  // the commit below happens after every thread read s
+    if (s >= 0) continue;  // block-uniform
+    const RP b = rp[v], e = rp[v + 1];
+    if (PHASE == kSpec) {
+      int t = spec_block<RP>(a.colidx, a.st, b, e, sm);
+      if (threadIdx.x == 0) a.st[v] = ~t;
+    } else {
+      const int t = ~s;
+      bool lose = detect_block<RP, SORTED>(a.colidx, a.st, b, e, v, t);
+      if (threadIdx.x == 0) {
+        if (!lose) a.st[v] = t;
+        tl.lost += lose;
+      }
+    }
+    if (threadIdx.x == 0) tl.active += 1;
+  }
+}
+
+// A whole phase of round r over every uncoloured vertex, by one block of a
+// grid of nblk blocks.  Detect also publishes whether round r + 1 has work
+// (more[(r+1) % 3]), clears more[(r+2) % 3] for the round after, and records
+// r as the last non-empty round and |U_r| in the trace.
+template <typename RP, int L, int PHASE, bool SORTED>
+__device__ void phase(const KArgs& a, int r, long blk, long nblk, HeavySmem& sm) {
+  Tally tl{0, 0};
+  if (PHASE == kDetect && blk == 0 && threadIdx.x == 0) a.ctrl->more[(r + 2) % 3].v = 0;
+  heavy_phase<RP, PHASE, SORTED>(a, blk, nblk, tl, sm);
+  const long wave_gid = blk * kWavesPerBlock + threadIdx.x / kWave;
+  const long nwaves = nblk * kWavesPerBlock;
+  medium_phase<RP, PHASE, SORTED>(a, wave_gid, nwaves, tl);
+  light_phase<RP, L, PHASE, SORTED>(a, wave_gid, nwaves, tl);
+  if (PHASE == kDetect) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      sm.active = 0;
+      sm.lost = 0;
+    }
+    __syncthreads();
+    if (tl.active) atomicAdd(&sm.active, tl.active);
+    if (tl.lost) atomicAdd(&sm.lost, tl.lost);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      if (sm.lost) a.ctrl->more[(r + 1) % 3].v = 1;
+      if (sm.active) {
+        a.ctrl->last_round.v = r;
+        if (r - 1 < kTraceRounds) atomicAdd(&a.ctrl->trace[r - 1], sm.active);
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------- kernels --
+
+template <typename RP, int L, int PHASE, bool SORTED>
+__global__ __launch_bounds__(kBlock) void k_phase(KArgs a, int round, int from_base) {
+  __shared__ HeavySmem sm;
+  const int r = from_base ? a.ctrl->round_base.v + round : round;
+  if (!a.ctrl->more[r % 3].v) {
+    if (PHASE == kDetect && blockIdx.x == 0 && threadIdx.x == 0) a.ctrl->more[(r + 2) % 3].v = 0;
+    return;
+  }
+  phase<RP, L, PHASE, SORTED>(a, r, blockIdx.x, gridDim.x, sm);
+}
+
+__global__ void k_init(KArgs a) {
+  const long tid = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const long nth = (long)gridDim.x * blockDim.x;
+  for (long v = tid; v < a.n; v += nth) a.st[v] = -1;  // tentative colour 0
+  for (long i = tid; i < kTraceRounds; i += nth) a.ctrl->trace[i] = 0;
+  if (tid == 0) {
+    a.ctrl->more[0].v = 0;
+    a.ctrl->more[1].v = a.n > 0;  // round 1 has work iff there are vertices
+    a.ctrl->more[2].v = 0;
+    a.ctrl->last_round.v = 0;
+    a.ctrl->round_base.v = 2;
+    a.ctrl->ncolors.v = 0;
+    a.ctrl->bar.v = 0;
+    a.ctrl->abort.v = 0;
+    a.ctrl->left.v = 0;
+  }
+}
+
+__global__ void k_advance_base(Ctrl* c, int by) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) c->round_base.v += by;
+}
+
+__global__ __launch_bounds__(kBlock) void k_finish(KArgs a) {
+  __shared__ int sh_max, sh_left;
+  if (threadIdx.x == 0) {
+    sh_max = -1;
+    sh_left = 0;
+  }
+  __syncthreads();
+  int mx = -1, left = 0;
+  const long tid = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const long nth = (long)gridDim.x * blockDim.x;
+  for (long v = tid; v < a.n; v += nth) {
+    int s = a.st[v];
+    mx = s > mx ? s : mx;
+    left += s < 0;
+  }
+  if (mx >= 0) atomicMax(&sh_max, mx);
+  if (left) atomicAdd(&sh_left, left);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (sh_max >= 0) atomicMax(&a.ctrl->ncolors.v, sh_max + 1);
+    if (sh_left) atomicAdd(&a.ctrl->left.v, sh_left);
+  }
+}
+
+// Grid-wide barrier of a co-resident (cooperative) grid.  Arrivals count up
+// monotonically; each block waits for epoch * gridDim.x.  Release/acquire at
+// agent scope make every block's writes visible across the XCDs' L2s.  A
+// wait that exceeds the spin limit sets ctrl->abort, and every later
+// barrier returns at once, so the kernel always drains.
+__device__ __forceinline__ bool grid_barrier(Ctrl* c, unsigned& epoch) {
+  __shared__ int sh_abort;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    ++epoch;
+    const unsigned target = epoch * gridDim.x;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_fetch_add((unsigned*)&c->bar.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int ab = __hip_atomic_load(&c->abort.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    long spins = 0;
+    while (!ab && __hip_atomic_load((unsigned*)&c->bar.v, __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > (1l << 25)) {
+        __hip_atomic_store(&c->abort.v, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ab = 1;
+      } else if ((spins & 1023) == 0) {
+        ab = __hip_atomic_load(&c->abort.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    sh_abort = ab;
+  }
+  __syncthreads();
+  return sh_abort == 0;
+}
+
+// The whole colouring in one launch: round 1 (detect only), then rounds of
+// speculate / barrier / detect / barrier until a round has no losers.
+template <typename RP, int L, bool SORTED>
+__global__ __launch_bounds__(kBlock) void k_persistent(KArgs a, int max_rounds) {
+  __shared__ HeavySmem sm;
+  unsigned epoch = 0;
+  phase<RP, L, kDetect, SORTED>(a, 1, blockIdx.x, gridDim.x, sm);
+  if (!grid_barrier(a.ctrl, epoch)) return;
+  for (int r = 2; max_rounds <= 0 || r <= max_rounds; ++r) {
+    const int more = __hip_atomic_load(&a.ctrl->more[r % 3].v, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+    if (!more) break;  // grid-uniform: read after a barrier, written before it
+    phase<RP, L, kSpec, SORTED>(a, r, blockIdx.x, gridDim.x, sm);
+    if (!grid_barrier(a.ctrl, epoch)) return;
+    phase<RP, L, kDetect, SORTED>(a, r, blockIdx.x, gridDim.x, sm);
+    if (!grid_barrier(a.ctrl, epoch)) return;
+  }
+}
+
+// ------------------------------------------------------ graph set-up --
+
+// Degree classes: medium (light_max < deg < heavy_min) and heavy
+// (deg >= heavy_min) vertex lists; counts[2] receives the maximum degree.
+template <typename RP>
+__global__ void k_classify(const RP* rowptr, int32_t n, int32_t light_max, int32_t heavy_min,
+                           int32_t* mlist, int32_t* hlist, int32_t* counts) {
+  __shared__ int sh_max;
+  if (threadIdx.x == 0) sh_max = 0;
+  __syncthreads();
+  int mx = 0;
+  const long tid = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const long nth = (long)gridDim.x * blockDim.x;
+  for (long v = tid; v < n; v += nth) {
+    RP d = rowptr[v + 1] - rowptr[v];
+    int di = d > (RP)INT_MAX ? INT_MAX : (int)d;
+    mx = di > mx ? di : mx;
+    if (di > light_max) {
+      if (di >= heavy_min) hlist[atomicAdd(&counts[1], 1)] = (int)v;
+      else mlist[atomicAdd(&counts[0], 1)] = (int)v;
+    }
+  }
+  atomicMax(&sh_max, mx);
+  __syncthreads();
+  if (threadIdx.x == 0) atomicMax(&counts[2], sh_max);
+}
+
+// CSR checks.  err[0] receives the smallest failing check code (0 = fine),
+// err[1] the vertex (or entry) where one failure of that code was seen:
+//   1 rowptr[0] != 0 or rowptr[n] != m     2 rowptr decreases
+//   3 neighbour id out of range             4 self-loop
+//   5 duplicate entry in a row              6 row not ascending (sorted mode)
+//   7 edge (v, u) without (u, v)
+template <typename RP, bool SORTED>
+__global__ void k_validate(const RP* rowptr, const int32_t* colidx, int32_t n, int64_t m,
+                           int32_t* err) {
+  const long tid = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const long nth = (long)gridDim.x * blockDim.x;
+  auto fail = [&](int code, long where) {
+    int old = atomicMin(&err[0], code);
+    if (code <= old) err[1] = (int)where;
+  };
+  if (tid == 0 && (rowptr[0] != 0 || (int64_t)rowptr[n] != m)) fail(1, 0);
+  for (long v = tid; v < n; v += nth) {
+    RP b = rowptr[v], e = rowptr[v + 1];
+    if (e < b || b < 0 || (int64_t)e > m) {
+      fail(2, v);
+      continue;
+    }
+    for (RP k = b; k < e; ++k) {
+      int u = colidx[k];
+      if (u < 0 || u >= n) {
+        fail(3, v);
+        continue;
+      }
+      if (u == v) fail(4, v);
+      if (k > b) {
+        int p = colidx[k - 1];
+        if (p == u) fail(5, v);
+        else if (SORTED && p > u) fail(6, v);
+      }
+      if (!SORTED) {
+        for (RP j = b; j < k; ++j)
+          if (colidx[j] == u) fail(5, v);
+      }
+      // symmetry: v must appear in row u
+      RP ub = rowptr[u], ue = rowptr[u + 1];
+      if (ue < ub || ub < 0 || (int64_t)ue > m) continue;  // reported at u
+      bool found = false;
+      if (SORTED) {
+        RP lo = ub, hi = ue;
+        while (lo < hi) {
+          RP mid = lo + (hi - lo) / 2;
+          if (colidx[mid] < v) lo = mid + 1;
+          else hi = mid;
+        }
+        found = lo < ue && colidx[lo] == v;
+      } else {
+        for (RP j = ub; j < ue && !found; ++j) found = colidx[j] == v;
+      }
+      if (!found) fail(7, v);
+    }
+  }
+}
+
+// ------------------------------------------------------ host launchers --
+
+template <typename RP, int L, bool SORTED>
+static int launch_round_t(const KArgs& a, int phase_id, int round, bool from_base, int grid,
+                          hipStream_t s) {
+  if (phase_id == kSpec)
+    hipLaunchKernelGGL((k_phase<RP, L, kSpec, SORTED>), dim3(grid), dim3(kBlock), 0, s, a, round,
+                       (int)from_base);
+  else
+    hipLaunchKernelGGL((k_phase<RP, L, kDetect, SORTED>), dim3(grid), dim3(kBlock), 0, s, a,
+                       round, (int)from_base);
+  return (int)hipGetLastError();
+}
+
+template <typename RP, int L, bool SORTED>
+static int launch_persistent_t(const KArgs& a, int max_rounds, int grid, hipStream_t s) {
+  KArgs aa = a;
+  int mr = max_rounds;
+  void* args[] = {&aa, &mr};
+  return (int)hipLaunchCooperativeKernel((const void*)&k_persistent<RP, L, SORTED>, dim3(grid),
+                                         dim3(kBlock), args, 0, s);
+}
+
+template <typename RP, int L, bool SORTED>
+static int persistent_grid_t(int* grid_out) {
+  int dev = 0, per_cu = 0, cus = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return (int)e;
+  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return (int)e;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)&k_persistent<RP, L, SORTED>,
+                                                   kBlock, 0);
+  if (e != hipSuccess) return (int)e;
+  *grid_out = per_cu * cus;
+  return 0;
+}
+
+// Dispatch on (rowptr width, lanes, sorted rows) to the template instances.
+#define GC_DISPATCH_L(RP, SORTED, FN, ...)             \
+  switch (lanes) {                                     \
+    case 1: return FN<RP, 1, SORTED>(__VA_ARGS__);     \
+    case 2: return FN<RP, 2, SORTED>(__VA_ARGS__);     \
+    case 4: return FN<RP, 4, SORTED>(__VA_ARGS__);     \
+    case 8: return FN<RP, 8, SORTED>(__VA_ARGS__);     \
+    case 16: return FN<RP, 16, SORTED>(__VA_ARGS__);   \
+    case 32: return FN<RP, 32, SORTED>(__VA_ARGS__);   \
+    case 64: return FN<RP, 64, SORTED>(__VA_ARGS__);   \
+    default: return (int)hipErrorInvalidValue;         \
+  }
+
+#define GC_DISPATCH(FN, ...)                                            \
+  do {                                                                  \
+    if (rp64) {                                                         \
+      if (sorted) { GC_DISPATCH_L(int64_t, true, FN, __VA_ARGS__) }     \
+      else { GC_DISPATCH_L(int64_t, false, FN, __VA_ARGS__) }           \
+    } else {                                                            \
+      if (sorted) { GC_DISPATCH_L(int32_t, true, FN, __VA_ARGS__) }     \
+      else { GC_DISPATCH_L(int32_t, false, FN, __VA_ARGS__) }           \
+    }                                                                   \
+  } while (0)
+
+int launch_round(const KArgs& a, bool rp64, bool sorted, int lanes, int phase_id, int round,
+                 bool round_from_base, int grid, void* stream) {
+  GC_DISPATCH(launch_round_t, a, phase_id, round, round_from_base, grid, (hipStream_t)stream);
+}
+
+int launch_persistent(const KArgs& a, bool rp64, bool sorted, int lanes, int max_rounds, int grid,
+                      void* stream) {
+  GC_DISPATCH(launch_persistent_t, a, max_rounds, grid, (hipStream_t)stream);
+}
+
+int persistent_max_grid(bool rp64, bool sorted, int lanes, int* grid_out) {
+  GC_DISPATCH(persistent_grid_t, grid_out);
+}
+
+int launch_init(const KArgs& a, void* stream, int grid) {
+  hipLaunchKernelGGL(k_init, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, a);
+  return (int)hipGetLastError();
+}
+
+int launch_advance_base(const KArgs& a, int by, void* stream) {
+  hipLaunchKernelGGL(k_advance_base, dim3(1), dim3(64), 0, (hipStream_t)stream, a.ctrl, by);
+  return (int)hipGetLastError();
+}
+
+int launch_finish(const KArgs& a, int grid, void* stream) {
+  hipLaunchKernelGGL(k_finish, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, a);
+  return (int)hipGetLastError();
+}
+
+int launch_classify(const void* rowptr, bool rp64, int32_t n, int32_t light_max, int32_t heavy_min,
+                    int32_t* mlist, int32_t* hlist, int32_t* counts, int grid, void* stream) {
+  if (rp64)
+    hipLaunchKernelGGL(k_classify<int64_t>, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream,
+                       (const int64_t*)rowptr, n, light_max, heavy_min, mlist, hlist, counts);
+  else
+    hipLaunchKernelGGL(k_classify<int32_t>, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream,
+                       (const int32_t*)rowptr, n, light_max, heavy_min, mlist, hlist, counts);
+  return (int)hipGetLastError();
+}
+
+int launch_validate(const void* rowptr, bool rp64, const int32_t* colidx, int32_t n, int64_t m,
+                    bool sorted, int32_t* err, int grid, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  if (rp64) {
+    if (sorted)
+      hipLaunchKernelGGL((k_validate<int64_t, true>), dim3(grid), dim3(kBlock), 0, s,
+                         (const int64_t*)rowptr, colidx, n, m, err);
+    else
+      hipLaunchKernelGGL((k_validate<int64_t, false>), dim3(grid), dim3(kBlock), 0, s,
+                         (const int64_t*)rowptr, colidx, n, m, err);
+  } else {
+    if (sorted)
+      hipLaunchKernelGGL((k_validate<int32_t, true>), dim3(grid), dim3(kBlock), 0, s,
+                         (const int32_t*)rowptr, colidx, n, m, err);
+    else
+      hipLaunchKernelGGL((k_validate<int32_t, false>), dim3(grid), dim3(kBlock), 0, s,
+                         (const int32_t*)rowptr, colidx, n, m, err);
+  }
+  return (int)hipGetLastError();
+}
+
+}  // namespace gc

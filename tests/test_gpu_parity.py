@@ -1,0 +1,275 @@
+"""GPU parity: the HIP colouring through the C ABI, bit for bit against the
+CPU oracle (colours and round count), on every round driver, every lane
+width, forced degree-class paths, sorted and unsorted rows, int32 and int64
+row pointers, the degenerate graphs, and the full-size workloads.
+
+Integer work: the bar is exact equality (no tolerance)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from conftest import ROOT
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+MODES = ["host", "chunked", "graph", "persistent"]
+GOLDEN = json.load(open(os.path.join(ROOT, "tests", "golden", "workloads.json")))
+
+
+@pytest.fixture(scope="module")
+def gc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1509_08267_amd import gc as gcmod
+    gcmod.load()
+    return gcmod
+
+
+def _dev(g, rp64=False):
+    rp = torch.from_numpy(g.rowptr.astype(np.int64 if rp64 else np.int32)).cuda()
+    ci = torch.from_numpy(g.colidx if g.nnz else np.zeros(0, np.int32)).cuda()
+    return rp, ci
+
+
+def gpu_color(gc, g, *, mode="persistent", rp64=False, rows_sorted=True, validate=True, **opts):
+    rp, ci = _dev(g, rp64)
+    with gc.Graph(rp, ci, validate=validate, rows_sorted=rows_sorted, mode=mode, **opts) as G:
+        out = G.color()
+        rounds, ncol = G.stats()
+        sizes = G.round_sizes()
+    return out.cpu().numpy(), rounds, ncol, sizes
+
+
+def assert_parity(gc, g, ref=None, **kw):
+    ref = ref or oracle.rsc(g.rowptr, g.colidx)
+    col, rounds, ncol, sizes = gpu_color(gc, g, **kw)
+    assert rounds == ref.rounds, (rounds, ref.rounds, kw)
+    assert np.array_equal(col, ref.colors), kw
+    assert ncol == ref.num_colors
+    assert np.array_equal(sizes[: ref.rounds], ref.trace[:, 0]), kw
+    return col
+
+
+def _named_cases():
+    return [
+        ("K1", graphgen.complete(1)), ("K2", graphgen.complete(2)), ("K65", graphgen.complete(65)),
+        ("K130", graphgen.complete(130)), ("path1", graphgen.path(1)), ("path2", graphgen.path(2)),
+        ("path1001", graphgen.path(1001)), ("C5", graphgen.cycle(5)), ("C9", graphgen.cycle(9)),
+        ("C10", graphgen.cycle(10)),
+        ("P6", graphgen.from_edges(6, [(0, 1), (1, 2), (2, 3), (3, 5), (4, 5)])),
+        ("star_lo", graphgen.star(300, 0)), ("star_hi", graphgen.star(300, 300)),
+        ("crown8", graphgen.crown(8)), ("empty7", graphgen.empty(7)),
+        ("er_small", graphgen.er(3000, 24000, 11)),
+    ]
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_named_graphs_every_mode(gc, mode):
+    for name, g in _named_cases():
+        print(f"[case] {name} mode={mode}", flush=True)
+        assert_parity(gc, g, mode=mode)
+
+
+def test_no_vertices(gc):
+    g = graphgen.CSR(np.zeros(1, np.int64), np.zeros(0, np.int32))
+    for mode in MODES:
+        col, rounds, ncol, _ = gpu_color(gc, g, mode=mode)
+        assert col.size == 0 and rounds == 0 and ncol == 0
+
+
+@pytest.mark.parametrize("lanes", [1, 2, 4, 8, 16, 32, 64])
+def test_every_lane_width(gc, lanes):
+    for seed, (n, m) in enumerate([(5000, 60000), (777, 20000)]):
+        g = graphgen.er(n, m, 100 + seed)
+        print(f"[case] er n={n} m={m} lanes={lanes}", flush=True)
+        assert_parity(gc, g, lanes=lanes, mode="persistent")
+        assert_parity(gc, g, lanes=lanes, mode="chunked")
+
+
+def test_forced_medium_and_heavy_paths(gc):
+    # thresholds low enough that ordinary vertices take the wavefront and
+    # workgroup paths
+    g = graphgen.er(4000, 80000, 21)
+    ref = oracle.rsc(g.rowptr, g.colidx)
+    for medium, heavy in [(4, 30), (0, 1), (1, 2), (16, 40), (64, 100000)]:
+        for mode in ("persistent", "host"):
+            print(f"[case] classes medium={medium} heavy={heavy} mode={mode}", flush=True)
+            assert_parity(gc, g, ref, mode=mode, medium_degree=medium or 1, heavy_degree=heavy)
+
+
+def test_multiword_colour_windows(gc):
+    # K_n needs colours up to n-1: beyond 64 (light/medium window) and with
+    # heavy_degree small, beyond nothing; K_4200 would exceed the 4096-bit
+    # heavy window but is large, so use a dense graph with heavy_degree low
+    g = graphgen.complete(300)
+    for medium, heavy in [(0, 100000), (1, 100000), (1, 2)]:
+        print(f"[case] K300 medium={medium} heavy={heavy}", flush=True)
+        assert_parity(gc, g, mode="persistent", medium_degree=medium or 400, heavy_degree=heavy)
+
+
+def test_unsorted_rows_and_int64_rowptr(gc):
+    rng = np.random.default_rng(5)
+    for g in (graphgen.er(3000, 30000, 7), graphgen.rmat(11, 8, .57, .19, .19, 2)):
+        ref = oracle.rsc(g.rowptr, g.colidx)
+        gs = graphgen.shuffle_rows(g, rng)
+        for rp64 in (False, True):
+            for sorted_rows, gg in ((True, g), (False, gs)):
+                print(f"[case] n={g.n} rp64={rp64} sorted={sorted_rows}", flush=True)
+                assert_parity(gc, gg, ref, rp64=rp64, rows_sorted=sorted_rows, mode="persistent")
+                assert_parity(gc, gg, ref, rp64=rp64, rows_sorted=sorted_rows, mode="host",
+                              medium_degree=8, heavy_degree=64)
+
+
+def test_random_small_graphs(gc):
+    rng = np.random.default_rng(42)
+    for i in range(120):
+        n = int(rng.integers(1, 60))
+        g = graphgen.random_small(n, float(rng.choice([0.05, 0.2, 0.6])), rng)
+        mode = MODES[i % len(MODES)]
+        assert_parity(gc, g, mode=mode, lanes=int(rng.choice([1, 4, 16, 64])))
+
+
+def test_validation_rejects_malformed_graphs(gc):
+    def create(rp, ci, n, m, flags):
+        return gc.gc_create(torch.tensor(rp, dtype=torch.int32).cuda(),
+                            torch.tensor(ci, dtype=torch.int32).cuda(), n, m, flags)
+
+    V = gc.GC_VALIDATE | gc.GC_ROWS_SORTED
+    bad = {
+        "self-loop": ([0, 1, 2], [0, 0], 2, 2),
+        "range": ([0, 1, 2], [1, 5], 2, 2),
+        "asymmetric": ([0, 1, 1], [1, 0], 2, 1),
+        "duplicate": ([0, 2, 4], [1, 1, 0, 0], 2, 4),
+        "unsorted": ([0, 2, 3, 4], [2, 1, 0, 0], 3, 4),
+        "rowptr": ([0, 2, 1], [1, 0], 2, 2),
+        "total": ([0, 1, 2], [1, 0], 2, 3),
+    }
+    for name, (rp, ci, n, m) in bad.items():
+        with pytest.raises(gc.GCError) as ei:
+            create(rp, ci, n, m, V)
+        assert ei.value.code == gc.GC_EINVAL, name
+    h = create([0, 1, 2], [1, 0], 2, 2, V)   # a single edge is fine
+    gc.gc_destroy(h)
+
+
+def test_round_cap_reports_erounds(gc):
+    g = graphgen.path(200)
+    rp, ci = _dev(g)
+    for mode in ("host", "persistent", "chunked"):
+        with gc.Graph(rp, ci, mode=mode, max_rounds=5) as G:
+            G.color()
+            with pytest.raises(gc.GCError) as ei:
+                G.stats()
+            assert ei.value.code == gc.GC_EROUNDS
+
+
+def test_repeated_calls_and_reuse(gc):
+    g = graphgen.er(20000, 200000, 9)
+    ref = oracle.rsc(g.rowptr, g.colidx)
+    rp, ci = _dev(g)
+    with gc.Graph(rp, ci, mode="persistent") as G:
+        out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        for i in range(20):
+            out.fill_(12345)  # stale contents must not matter
+            G.color(out)
+            r, k = G.stats()
+            assert r == ref.rounds and np.array_equal(out.cpu().numpy(), ref.colors)
+        for mode in MODES:
+            G.set("mode", mode)
+            G.color(out)
+            assert G.stats()[0] == ref.rounds
+            assert np.array_equal(out.cpu().numpy(), ref.colors)
+
+
+def test_other_stream(gc):
+    g = graphgen.er(20000, 150000, 4)
+    ref = oracle.rsc(g.rowptr, g.colidx)
+    rp, ci = _dev(g)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        with gc.Graph(rp, ci, mode="persistent") as G:
+            out = G.color(stream=s)
+            G.stats()
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), ref.colors)
+
+
+def test_star_with_million_leaves(gc):
+    # one vertex of degree 10^6 on the workgroup path (and the leaves first)
+    for centre in (0, 1_000_000):
+        g = graphgen.star(1_000_000, centre)
+        col, rounds, _, _ = gpu_color(gc, g, mode="persistent")
+        expect = np.ones(g.n, np.int32) if centre == 0 else np.zeros(g.n, np.int32)
+        expect[centre] = 0 if centre == 0 else 1
+        assert rounds == 2 and np.array_equal(col, expect)
+
+
+def test_long_path_many_rounds(gc):
+    # natural-order path: floor(n/2) + 1 rounds, colour v mod 2
+    n = 20001
+    g = graphgen.path(n)
+    for mode in ("persistent", "graph"):
+        col, rounds, ncol, _ = gpu_color(gc, g, mode=mode)
+        assert rounds == n // 2 + 1
+        assert np.array_equal(col, np.arange(n, dtype=np.int32) % 2)
+
+
+def test_complete_2048(gc):
+    g = graphgen.complete(2048)
+    col, rounds, ncol, _ = gpu_color(gc, g, mode="persistent")
+    assert rounds == 2048 and ncol == 2048
+    assert np.array_equal(col, np.arange(2048, dtype=np.int32))
+
+
+# ------------------------------------------------------ full-size inputs --
+
+def _full(gc, name, **kw):
+    print(f"[case] workload {name} {kw}", flush=True)
+    g = graphgen.workload(name)
+    gold = GOLDEN[name]
+    assert g.sha256() == gold["input_sha256"]
+    rp64 = name == "rmat22_ef16"
+    col, rounds, ncol, sizes = gpu_color(gc, g, rp64=rp64, validate=False, **kw)
+    import hashlib
+    assert rounds == gold["rounds"]
+    assert ncol == gold["num_colors"]
+    assert hashlib.sha256(col.astype(np.int32).tobytes()).hexdigest() == gold["colors_sha256"]
+    assert list(sizes[:rounds]) == gold["round_sizes"]
+    return g, col
+
+
+@pytest.mark.slow
+def test_workload_er_10k(gc):
+    g, col = _full(gc, "er_10k_100k")
+    ref = oracle.rsc(g.rowptr, g.colidx)
+    assert np.array_equal(col, ref.colors)
+    for mode in MODES:
+        _full(gc, "er_10k_100k", mode=mode)
+
+
+@pytest.mark.slow
+def test_workload_er_1m(gc):
+    g, col = _full(gc, "er_1m_16m")
+    ref = oracle.rsc(g.rowptr, g.colidx)   # the oracle itself, a few seconds
+    assert np.array_equal(col, ref.colors)
+    assert oracle.check_proper(g.rowptr, g.colidx, col) == 0
+
+
+@pytest.mark.slow
+def test_workload_stencil(gc):
+    g, col = _full(gc, "stencil27_160")
+    assert oracle.check_proper(g.rowptr, g.colidx, col) == 0
+    assert oracle.check_grundy(g.rowptr, g.colidx, col) == 0
+
+
+@pytest.mark.slow
+def test_workload_rmat(gc):
+    g, col = _full(gc, "rmat22_ef16")
+    assert oracle.check_proper(g.rowptr, g.colidx, col) == 0
+    assert oracle.check_grundy(g.rowptr, g.colidx, col) == 0
