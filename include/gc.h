@@ -94,12 +94,14 @@ int gc_create(gc_handle *out, const void *rowptr, const int32_t *colidx,
 /*
  * gc_color -- colour the bound graph.
  *
- *   colors_out  device, n int32 entries; receives colour(v) in 0..deg(v).
- *               It is also the working state during the call (its prior
- *               contents are ignored).
- *   stream      all work is queued here; the call returns before the
- *               colouring is finished except in GC_MODE_HOST, which reads a
- *               counter back every round.
+ *   colors_out  device, n int32 entries; receives colour(v) in 0..deg(v)
+ *               (its prior contents are ignored).  The working state is a
+ *               library-owned array of 1, 2 or 4 bytes per vertex (by maximum
+ *               degree), widened into colors_out at the end.
+ *   stream      all work is queued here.  The first call on a handle reads a
+ *               4-byte flag back every few rounds to find the round count R;
+ *               later calls queue all R rounds and return at once (R depends
+ *               on the graph only).  GC_MODE_HOST reads back every round.
  *
  * One handle serves one call at a time: a second gc_color before the first
  * has been observed finished (gc_get_stats / stream sync) returns GC_EBUSY
@@ -113,7 +115,9 @@ int gc_color(gc_handle h, int32_t *colors_out, void *stream);
  * Waits for that call's stream.  `rounds` receives the number of rounds R
  * (0 when n = 0), `num_colors` max colour + 1 (0 when n = 0).  Either
  * pointer may be NULL.  Returns GC_EROUNDS if the call stopped at the round
- * cap with vertices still uncoloured.
+ * cap (GC_OPT_MAX_ROUNDS) with vertices still uncoloured, GC_EINVAL if
+ * vertices were left uncoloured otherwise (the graph arrays were changed
+ * after gc_create, against the contract), GC_EDEVICE on a device error.
  */
 int gc_get_stats(gc_handle h, int64_t *rounds, int32_t *num_colors);
 
@@ -141,11 +145,13 @@ enum gc_option {
   GC_OPT_MAX_DEGREE = 8,     /* (get only) maximum degree of the graph              */
   GC_OPT_MEDIUM_COUNT = 9,   /* (get only) vertices on the wavefront path           */
   GC_OPT_HEAVY_COUNT = 10,   /* (get only) vertices on the workgroup path           */
-  GC_OPT_PERSISTENT_BLOCKS_PER_CU = 11 /* workgroups per CU of the persistent kernel,
+  GC_OPT_PERSISTENT_BLOCKS_PER_CU = 11, /* workgroups per CU of the persistent kernel,
                                 1..6 (4); more are not reliably co-resident   */
+  GC_OPT_STATE_BYTES = 12    /* (get only) bytes per vertex of the working state:
+                                1 if max degree <= 127, 2 if <= 32767, else 4 */
 };
 enum gc_mode {
-  GC_MODE_AUTO = 0,       /* currently PERSISTENT                                 */
+  GC_MODE_AUTO = 0,       /* currently GRAPH                                      */
   GC_MODE_HOST = 1,       /* one round per host iteration, a flag read back       */
   GC_MODE_CHUNKED = 2,    /* rounds queued in chunks; empty rounds exit at once   */
   GC_MODE_PERSISTENT = 3, /* one cooperative kernel, device-side round loop      */

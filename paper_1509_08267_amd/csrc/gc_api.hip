@@ -2,13 +2,17 @@
 // management, argument checks, the round drivers and result read-back.
 //
 // Round drivers (GC_OPT_MODE):
-//   HOST        one speculate + detect launch pair per round, then a 4-byte
-//               read-back of "does the next round have work".
-//   CHUNKED     rounds are queued GC_OPT_CHUNK_ROUNDS at a time; a round
-//               whose set is empty returns at once, so over-queueing is
-//               harmless; one read-back per chunk.
-//   GRAPH       as CHUNKED, but the chunk is a captured hipGraph replayed
-//               with a device-side round base.
+//   GRAPH       (default) rounds run as captured hipGraphs of K rounds each
+//               (speculate + detect launches with a device-side round base),
+//               so back-to-back kernels need no host launch per round.  The
+//               first call on a handle learns the round count R with one
+//               4-byte read-back per chunk; because R is a function of the
+//               (unchanged) graph alone, later calls queue exactly R - 1
+//               rounds after round 1 and never wait on the host.  If the
+//               graph was modified against the contract, vertices are left
+//               uncoloured and gc_get_stats reports it.
+//   CHUNKED     as GRAPH with direct launches.
+//   HOST        one speculate + detect pair per round, then a read-back.
 //   PERSISTENT  one cooperative launch runs every round with grid barriers.
 // All drivers run the same phase code and give the same bits.
 #include <hip/hip_runtime.h>
@@ -42,6 +46,12 @@ struct Pinned {  // read-back area in pinned host memory
   int32_t pad1[3];
 };
 
+struct Captured {  // one instantiated chunk of K rounds
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int k = 0, lanes = 0, light = 0;
+};
+
 }  // namespace
 
 struct gc_ctx {
@@ -54,6 +64,8 @@ struct gc_ctx {
   uint32_t flags = 0;
 
   Ctrl* ctrl = nullptr;       // device
+  void* state = nullptr;      // device, n * sbytes
+  int sbytes = 4;             // state width (1, 2 or 4 bytes) from the max degree
   int32_t* mlist = nullptr;   // device, n
   int32_t* hlist = nullptr;   // device, n
   int32_t* dcounts = nullptr; // device, 8 ints: classify counts, validate err
@@ -66,21 +78,19 @@ struct gc_ctx {
   int medium_min = 0;     // 0 = auto (deg > medium threshold -> medium)
   int heavy_min = 4096;   // deg >= heavy_min -> heavy
   int blocks_per_cu = 8;
-  int persist_per_cu = 4;  // co-resident workgroups per CU of the persistent kernel
+  int persist_per_cu = 4; // co-resident workgroups per CU of the persistent kernel
   int max_rounds = 0;
-  int chunk_rounds = 8;
+  int chunk_rounds = 16;
   bool lists_dirty = false;
 
   // last colouring
   hipEvent_t done = nullptr;
   bool in_flight = false;
   bool stats_ready = false;
+  int64_t known_rounds = 0;  // R of this graph once a call has completed (0 = unknown)
 
-  // captured chunk (GRAPH mode)
-  hipGraphExec_t gexec = nullptr;
-  hipGraph_t graph = nullptr;
-  int32_t* g_st = nullptr;
-  int g_chunk = 0, g_lanes = 0, g_light = 0;
+  Captured chunk;  // discovery chunk (chunk_rounds)
+  Captured exact;  // R - 1 rounds, once R is known
 
   std::string err;
 };
@@ -105,12 +115,18 @@ static int set_err(gc_ctx* h, int code, const char* fmt, ...) {
                      __FILE__, __LINE__);                                             \
   } while (0)
 
+#define LCHECK(h, expr)                                                                   \
+  do {                                                                                    \
+    int r_ = (expr);                                                                      \
+    if (r_) return set_err(h, GC_EDEVICE, "%s: %s", #expr, hipGetErrorString((hipError_t)r_)); \
+  } while (0)
+
 static int auto_lanes(const gc_ctx* h) {
   if (h->lanes) return h->lanes;
   double avg = h->n ? (double)h->m / (double)h->n : 0.0;
-  int L = 1;
+  int L = 2;
   while (L < 32 && L * 2 <= avg) L *= 2;  // about two entries per lane
-  return std::max(L, 2);
+  return L;
 }
 
 static int light_max_of(const gc_ctx* h, int L) {
@@ -118,17 +134,25 @@ static int light_max_of(const gc_ctx* h, int L) {
   return std::max(8 * L, 64);
 }
 
-static KArgs make_args(const gc_ctx* h, int32_t* st, int light_max) {
+static int state_bytes(int32_t maxdeg) {
+  if (maxdeg <= 127) return 1;
+  if (maxdeg <= 32767) return 2;
+  return 4;
+}
+
+static KArgs make_args(const gc_ctx* h, int32_t* colors, int light_max) {
   KArgs a{};
   a.rowptr = h->rowptr;
   a.colidx = h->colidx;
-  a.st = st;
+  a.st = h->state;
+  a.colors = colors;
   a.n = (int32_t)h->n;
   a.light_max = light_max;
   a.mlist = h->mlist;
   a.mcount = h->mcount;
   a.hlist = h->hlist;
   a.hcount = h->hcount;
+  a.sorted = (h->flags & GC_ROWS_SORTED) != 0;
   a.ctrl = h->ctrl;
   return a;
 }
@@ -141,9 +165,8 @@ static int classify(gc_ctx* h, hipStream_t s) {
   const int light = light_max_of(h, L);
   const int heavy = std::max(h->heavy_min, light + 1);
   HIPCHECK(h, hipMemsetAsync(h->dcounts, 0, 3 * sizeof(int32_t), s));
-  int rc = gc::launch_classify(h->rowptr, h->rp64, (int32_t)h->n, light, heavy, h->mlist, h->hlist,
-                               h->dcounts, grid_of(h), s);
-  if (rc) return set_err(h, GC_EDEVICE, "classify launch: %s", hipGetErrorString((hipError_t)rc));
+  LCHECK(h, gc::launch_classify(h->rowptr, h->rp64, (int32_t)h->n, light, heavy, h->mlist, h->hlist,
+                                h->dcounts, grid_of(h), s));
   HIPCHECK(h, hipMemcpyAsync(h->host->counts, h->dcounts, 3 * sizeof(int32_t),
                              hipMemcpyDeviceToHost, s));
   HIPCHECK(h, hipStreamSynchronize(s));
@@ -154,19 +177,19 @@ static int classify(gc_ctx* h, hipStream_t s) {
   return GC_OK;
 }
 
-static void free_graph(gc_ctx* h) {
-  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
-  if (h->graph) (void)hipGraphDestroy(h->graph);
-  h->gexec = nullptr;
-  h->graph = nullptr;
-  h->g_st = nullptr;
+static void drop(Captured& c) {
+  if (c.exec) (void)hipGraphExecDestroy(c.exec);
+  if (c.graph) (void)hipGraphDestroy(c.graph);
+  c = Captured();
 }
 
 static void free_ctx(gc_ctx* h) {
   if (!h) return;
-  free_graph(h);
+  drop(h->chunk);
+  drop(h->exact);
   if (h->done) (void)hipEventDestroy(h->done);
   if (h->ctrl) (void)hipFree(h->ctrl);
+  if (h->state) (void)hipFree(h->state);
   if (h->mlist) (void)hipFree(h->mlist);
   if (h->hlist) (void)hipFree(h->hlist);
   if (h->dcounts) (void)hipFree(h->dcounts);
@@ -249,6 +272,8 @@ extern "C" int gc_create(gc_handle* out, const void* rowptr, const int32_t* coli
     free_ctx(h);
     return rc;
   }
+  h->sbytes = state_bytes(h->maxdeg);
+  CREATE_CHECK(hipMalloc(&h->state, (size_t)std::max<int64_t>(n, 1) * h->sbytes));
   *out = h;
   return GC_OK;
 }
@@ -263,14 +288,16 @@ static int ensure_idle(gc_ctx* h) {
 }
 
 static int resolve_mode(const gc_ctx* h) {
-  int mode = h->mode == GC_MODE_AUTO ? GC_MODE_PERSISTENT : h->mode;
+  int mode = h->mode == GC_MODE_AUTO ? GC_MODE_GRAPH : h->mode;
   // a captured chunk cannot stop inside itself: honour a round cap by queueing
   if (mode == GC_MODE_GRAPH && h->max_rounds > 0) mode = GC_MODE_CHUNKED;
   return mode;
 }
 
-static int capture_chunk(gc_ctx* h, const KArgs& a, int L, int K) {
-  free_graph(h);
+// Capture K rounds (speculate + detect, rounds relative to the device-side
+// round base) and the base advance into c.
+static int capture(gc_ctx* h, Captured& c, const KArgs& a, int L, int K) {
+  drop(c);
   hipStream_t cs;
   HIPCHECK(h, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
   hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
@@ -279,10 +306,9 @@ static int capture_chunk(gc_ctx* h, const KArgs& a, int L, int K) {
     return set_err(h, GC_EDEVICE, "begin capture: %s", hipGetErrorString(e));
   }
   int rc = 0;
-  const bool sorted = (h->flags & GC_ROWS_SORTED) != 0;
   for (int j = 0; j < K && !rc; ++j) {
-    rc = gc::launch_round(a, h->rp64, sorted, L, 0, j, true, grid_of(h), cs);
-    if (!rc) rc = gc::launch_round(a, h->rp64, sorted, L, 1, j, true, grid_of(h), cs);
+    rc = gc::launch_round(a, h->rp64, h->sbytes, L, 0, j, true, grid_of(h), cs);
+    if (!rc) rc = gc::launch_round(a, h->rp64, h->sbytes, L, 1, j, true, grid_of(h), cs);
   }
   if (!rc) rc = gc::launch_advance_base(a, K, cs);
   hipGraph_t g = nullptr;
@@ -299,13 +325,16 @@ static int capture_chunk(gc_ctx* h, const KArgs& a, int L, int K) {
     (void)hipGraphDestroy(g);
     return set_err(h, GC_EDEVICE, "instantiate: %s", hipGetErrorString(e));
   }
-  h->graph = g;
-  h->gexec = x;
-  h->g_st = a.st;
-  h->g_chunk = K;
-  h->g_lanes = L;
-  h->g_light = a.light_max;
+  c.graph = g;
+  c.exec = x;
+  c.k = K;
+  c.lanes = L;
+  c.light = a.light_max;
   return GC_OK;
+}
+
+static bool usable(const Captured& c, int K, int L, int light) {
+  return c.exec && c.k == K && c.lanes == L && c.light == light;
 }
 
 extern "C" int gc_color(gc_handle h, int32_t* colors_out, void* stream) {
@@ -325,63 +354,66 @@ extern "C" int gc_color(gc_handle h, int32_t* colors_out, void* stream) {
   const int L = auto_lanes(h);
   const int light = light_max_of(h, L);
   const KArgs a = make_args(h, colors_out, light);
-  const bool sorted = (h->flags & GC_ROWS_SORTED) != 0;
   const int grid = grid_of(h);
   const int mode = resolve_mode(h);
 
-#define LCHECK(expr)                                                                      \
-  do {                                                                                    \
-    int r_ = (expr);                                                                      \
-    if (r_) return set_err(h, GC_EDEVICE, "%s: %s", #expr, hipGetErrorString((hipError_t)r_)); \
-  } while (0)
-
-  LCHECK(gc::launch_init(a, s, std::min(grid, 1024)));
+  LCHECK(h, gc::launch_init(a, s));
   if (mode == GC_MODE_PERSISTENT) {
     int maxg = 0;
-    LCHECK(gc::persistent_max_grid(h->rp64, sorted, L, &maxg));
+    LCHECK(h, gc::persistent_max_grid(h->rp64, h->sbytes, L, &maxg));
     // The occupancy query admits more workgroups per CU than are co-resident in
     // practice (a barrier with 7-8 per CU never completes on MI355X), so the
     // grid is capped at persist_per_cu per CU, which has been verified.
     int pg = std::min(maxg, h->cus * h->persist_per_cu);
     if (pg < 1) return set_err(h, GC_EDEVICE, "persistent kernel cannot be resident");
-    LCHECK(gc::launch_persistent(a, h->rp64, sorted, L, h->max_rounds, pg, s));
+    LCHECK(h, gc::launch_persistent(a, h->rp64, h->sbytes, L, h->max_rounds, pg, s));
   } else {
-    LCHECK(gc::launch_round(a, h->rp64, sorted, L, 1, 1, false, grid, s));  // round 1
+    LCHECK(h, gc::launch_round1(a, h->rp64, h->sbytes, L, grid, s));
     int r = 1;  // last round queued
-    const int K = std::max(1, h->chunk_rounds);
-    for (;;) {
-      HIPCHECK(h, hipMemcpyAsync(&h->host->flag, &h->ctrl->more[(r + 1) % 3].v, sizeof(int32_t),
-                                 hipMemcpyDeviceToHost, s));
-      HIPCHECK(h, hipStreamSynchronize(s));
-      if (!h->host->flag) break;
-      if (h->max_rounds > 0 && r >= h->max_rounds) break;
-      if (mode == GC_MODE_HOST) {
-        ++r;
-        LCHECK(gc::launch_round(a, h->rp64, sorted, L, 0, r, false, grid, s));
-        LCHECK(gc::launch_round(a, h->rp64, sorted, L, 1, r, false, grid, s));
-      } else if (mode == GC_MODE_CHUNKED) {
-        int upto = r + K;
-        if (h->max_rounds > 0) upto = std::min(upto, h->max_rounds);
-        for (int q = r + 1; q <= upto; ++q) {
-          LCHECK(gc::launch_round(a, h->rp64, sorted, L, 0, q, false, grid, s));
-          LCHECK(gc::launch_round(a, h->rp64, sorted, L, 1, q, false, grid, s));
-        }
-        r = upto;
-      } else if (mode == GC_MODE_GRAPH) {
-        if (!h->gexec || h->g_st != colors_out || h->g_chunk != K || h->g_lanes != L ||
-            h->g_light != light) {
-          rc = capture_chunk(h, a, L, K);
+    if (mode == GC_MODE_GRAPH && h->known_rounds > 0) {
+      // R is known: queue rounds 2..R in one captured chunk, no read-back.
+      const int K = (int)h->known_rounds - 1;
+      if (K > 0) {
+        if (!usable(h->exact, K, L, light)) {
+          rc = capture(h, h->exact, a, L, K);
           if (rc) return rc;
         }
-        HIPCHECK(h, hipGraphLaunch(h->gexec, s));
-        r += K;  // the chunk ran rounds r+1 .. r+K (round_base advanced by K)
-      } else {
-        return set_err(h, GC_EINVAL, "unknown mode %d", mode);
+        HIPCHECK(h, hipGraphLaunch(h->exact.exec, s));
+      }
+    } else {
+      const int K = std::max(1, h->chunk_rounds);
+      for (;;) {
+        HIPCHECK(h, hipMemcpyAsync(&h->host->flag, &h->ctrl->more[(r + 1) % 3].v, sizeof(int32_t),
+                                   hipMemcpyDeviceToHost, s));
+        HIPCHECK(h, hipStreamSynchronize(s));
+        if (!h->host->flag) break;
+        if (h->max_rounds > 0 && r >= h->max_rounds) break;
+        if (mode == GC_MODE_HOST) {
+          ++r;
+          LCHECK(h, gc::launch_round(a, h->rp64, h->sbytes, L, 0, r, false, grid, s));
+          LCHECK(h, gc::launch_round(a, h->rp64, h->sbytes, L, 1, r, false, grid, s));
+        } else if (mode == GC_MODE_CHUNKED) {
+          int upto = r + K;
+          if (h->max_rounds > 0) upto = std::min(upto, h->max_rounds);
+          for (int q = r + 1; q <= upto; ++q) {
+            LCHECK(h, gc::launch_round(a, h->rp64, h->sbytes, L, 0, q, false, grid, s));
+            LCHECK(h, gc::launch_round(a, h->rp64, h->sbytes, L, 1, q, false, grid, s));
+          }
+          r = upto;
+        } else if (mode == GC_MODE_GRAPH) {
+          if (!usable(h->chunk, K, L, light)) {
+            rc = capture(h, h->chunk, a, L, K);
+            if (rc) return rc;
+          }
+          HIPCHECK(h, hipGraphLaunch(h->chunk.exec, s));
+          r += K;  // rounds r+1 .. r+K ran (the round base advanced by K)
+        } else {
+          return set_err(h, GC_EINVAL, "unknown mode %d", mode);
+        }
       }
     }
   }
-  LCHECK(gc::launch_finish(a, std::min(grid, 512), s));
-  static_assert(offsetof(Pinned, ncolors) == offsetof(Pinned, last_round) + 4, "layout");
+  LCHECK(h, gc::launch_finish(a, h->sbytes, std::min(grid, 1024), s));
   HIPCHECK(h, hipMemcpyAsync(&h->host->last_round, &h->ctrl->last_round.v, 4, hipMemcpyDeviceToHost, s));
   HIPCHECK(h, hipMemcpyAsync(&h->host->ncolors, &h->ctrl->ncolors.v, 4, hipMemcpyDeviceToHost, s));
   HIPCHECK(h, hipMemcpyAsync(&h->host->abort, &h->ctrl->abort.v, 4, hipMemcpyDeviceToHost, s));
@@ -399,8 +431,14 @@ static int wait_done(gc_ctx* h) {
     h->in_flight = false;
   }
   if (h->host->abort) return set_err(h, GC_EDEVICE, "persistent kernel: grid barrier timed out");
-  if (h->host->left) return set_err(h, GC_EROUNDS, "round cap reached with %d vertices uncoloured",
-                                    h->host->left);
+  if (h->host->left) {
+    if (h->max_rounds > 0 && h->host->last_round >= h->max_rounds)
+      return set_err(h, GC_EROUNDS, "round cap reached with %d vertices uncoloured", h->host->left);
+    h->known_rounds = 0;
+    return set_err(h, GC_EINVAL, "%d vertices uncoloured after the known %d rounds: the graph "
+                   "changed after gc_create", h->host->left, h->host->last_round);
+  }
+  if (h->max_rounds == 0) h->known_rounds = h->host->last_round;
   return GC_OK;
 }
 
@@ -444,7 +482,7 @@ extern "C" int gc_set_option(gc_handle h, int option, int64_t value) {
       h->mode = (int)value;
       return GC_OK;
     case GC_OPT_LANES:
-      if (value != 0 && (value < 1 || value > 64 || (value & (value - 1)))) break;
+      if (value != 0 && (value < 2 || value > 64 || (value & (value - 1)))) break;
       h->lanes = (int)value;
       h->lists_dirty = true;
       return GC_OK;
@@ -491,10 +529,11 @@ extern "C" int gc_get_option(gc_handle h, int option, int64_t* value) {
     case GC_OPT_BLOCKS_PER_CU: *value = h->blocks_per_cu; return GC_OK;
     case GC_OPT_MAX_ROUNDS: *value = h->max_rounds; return GC_OK;
     case GC_OPT_CHUNK_ROUNDS: *value = h->chunk_rounds; return GC_OK;
-    case GC_OPT_PERSISTENT_BLOCKS_PER_CU: *value = h->persist_per_cu; return GC_OK;
     case GC_OPT_MAX_DEGREE: *value = h->maxdeg; return GC_OK;
     case GC_OPT_MEDIUM_COUNT: *value = h->mcount; return GC_OK;
     case GC_OPT_HEAVY_COUNT: *value = h->hcount; return GC_OK;
+    case GC_OPT_PERSISTENT_BLOCKS_PER_CU: *value = h->persist_per_cu; return GC_OK;
+    case GC_OPT_STATE_BYTES: *value = h->sbytes; return GC_OK;
     default: return set_err(h, GC_EINVAL, "gc_get_option: unknown option %d", option);
   }
 }
@@ -514,4 +553,4 @@ extern "C" const char* gc_last_error(gc_handle h) {
   return h ? h->err.c_str() : tl_error.c_str();
 }
 
-extern "C" const char* gc_version(void) { return "0.1.0"; }
+extern "C" const char* gc_version(void) { return "0.2.0"; }

@@ -1,9 +1,13 @@
 // gc_internal.h -- shared between the C-ABI engine and the gfx950 kernels.
 //
-// State encoding (one int32 per vertex, the caller's colour array):
+// State encoding (one signed integer per vertex, of width S = int8, int16 or
+// int32 chosen from the maximum degree):
 //   s >= 0   the vertex's colour is final (= s)
 //   s <  0   the vertex is still being coloured; its tentative colour of the
 //            current round is ~s (so the initial -1 means "tentative 0")
+// Every colour and tentative colour is at most deg(v) (First Fit picks the
+// least of deg(v) + 1 candidates), so S = int8 holds any graph with maximum
+// degree <= 127 and int16 any with maximum degree <= 32767.
 // A round's speculate phase rewrites only negative entries (negative stays
 // negative), and its detect phase turns a winner's ~t into t.  A reader that
 // decodes (s < 0 ? ~s : s) therefore sees the same tentative colour before and
@@ -20,8 +24,8 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kTraceRounds = 65536; // rounds whose |U_r| is recorded
 constexpr int kHeavyWindow = 4096;  // LDS colour window of the block-per-vertex path (bits)
 
-// One 128-byte line per field group that different blocks write, so that
-// flags and counters never share a line.
+// One 128-byte line per field that different blocks write, so that flags and
+// counters never share a line.
 struct alignas(128) Line {
   int32_t v;
   int32_t pad[31];
@@ -32,9 +36,9 @@ struct Ctrl {
   Line last_round;       // last round that had uncoloured vertices
   Line round_base;       // first round of the next captured chunk
   Line ncolors;          // max colour + 1
-  Line bar;              // grid barrier arrivals (monotonic)
+  Line bar;              // grid barrier arrivals (monotonic within a launch)
   Line abort;            // set when a barrier wait exceeded its spin limit
-  Line left;             // vertices still uncoloured at the round cap
+  Line left;             // vertices still uncoloured after the last round
   int32_t trace[kTraceRounds];  // |U_r| at slot r - 1
 };
 
@@ -42,26 +46,29 @@ struct Ctrl {
 struct KArgs {
   const void* rowptr;     // int32 or int64, n + 1
   const int32_t* colidx;  // nnz
-  int32_t* st;            // n, the state / output colours
+  void* st;               // n entries of the state type
+  int32_t* colors;        // n, the caller's output (the widened state)
   int32_t n;
   int32_t light_max;      // deg <= light_max: a group of L lanes per vertex
-  const int32_t* mlist;   // medium vertices (light_max < deg <= heavy_min - 1): a wavefront each
+  const int32_t* mlist;   // medium vertices (light_max < deg < heavy): a wavefront each
   int32_t mcount;
   const int32_t* hlist;   // heavy vertices: a whole workgroup each
   int32_t hcount;
+  int32_t sorted;         // rows ascending: the conflict scan may stop early
   Ctrl* ctrl;
 };
 
 // Launch helpers implemented in gc_kernels.hip.  All return a hipError_t
-// cast to int.
-int launch_init(const KArgs& a, void* stream, int grid);
-int launch_round(const KArgs& a, bool rp64, bool sorted, int lanes, int phase /*0 spec, 1 detect*/,
+// cast to int.  `sbytes` is the state width in bytes (1, 2 or 4).
+int launch_init(const KArgs& a, void* stream);
+int launch_round1(const KArgs& a, bool rp64, int sbytes, int lanes, int grid, void* stream);
+int launch_round(const KArgs& a, bool rp64, int sbytes, int lanes, int phase /*0 spec, 1 detect*/,
                  int round, bool round_from_base, int grid, void* stream);
 int launch_advance_base(const KArgs& a, int by, void* stream);
-int launch_finish(const KArgs& a, int grid, void* stream);
-int launch_persistent(const KArgs& a, bool rp64, bool sorted, int lanes, int max_rounds,
-                      int grid, void* stream);
-int persistent_max_grid(bool rp64, bool sorted, int lanes, int* grid_out);
+int launch_finish(const KArgs& a, int sbytes, int grid, void* stream);
+int launch_persistent(const KArgs& a, bool rp64, int sbytes, int lanes, int max_rounds, int grid,
+                      void* stream);
+int persistent_max_grid(bool rp64, int sbytes, int lanes, int* grid_out);
 int launch_classify(const void* rowptr, bool rp64, int32_t n, int32_t light_max, int32_t heavy_min,
                     int32_t* mlist, int32_t* hlist, int32_t* counts /*[3]: medium, heavy, maxdeg*/,
                     int grid, void* stream);

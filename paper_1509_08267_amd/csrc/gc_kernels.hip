@@ -24,6 +24,10 @@
 // pick is find-first-zero.  Colours beyond the first 64 (or 4096 for heavy
 // vertices) are handled by sliding the window, which only happens when a
 // vertex sees that many distinct final colours.
+//
+// The per-vertex state is int8, int16 or int32 (template S) by maximum
+// degree: a narrower state keeps the gathered array resident in the L2 of
+// each XCD.  A final pass widens it into the caller's int32 colours.
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -86,9 +90,9 @@ __device__ __forceinline__ int tent_of(int s) { return s < 0 ? ~s : s; }
 
 // Least colour not final on any neighbour of the row [b, e), computed by a
 // group of L lanes (gl = lane in group).  Every lane returns the result.
-template <typename RP, int L>
+template <typename RP, typename S, int L>
 __device__ __forceinline__ int spec_group(const int32_t* __restrict__ colidx,
-                                          const int32_t* __restrict__ st, RP b, RP e,
+                                          const S* __restrict__ st, RP b, RP e,
                                           int gl) {
   int base = 0;
   for (;;) {
@@ -117,10 +121,10 @@ __device__ __forceinline__ int spec_group(const int32_t* __restrict__ colidx,
 
 // Does a lower-id neighbour of v carry tentative colour t?  Group of L lanes.
 // With sorted rows the scan stops at the first neighbour id >= v.
-template <typename RP, int L, bool SORTED>
+template <typename RP, typename S, int L>
 __device__ __forceinline__ bool detect_group(const int32_t* __restrict__ colidx,
-                                             const int32_t* __restrict__ st, RP b, RP e,
-                                             int v, int t, int gl, uint64_t gmask) {
+                                             const S* __restrict__ st, RP b, RP e,
+                                             int v, int t, int gl, uint64_t gmask, bool sorted) {
   for (RP kb = b; kb < e; kb += L) {
     RP k = kb + gl;
     bool conf = false, past = false;
@@ -135,7 +139,7 @@ __device__ __forceinline__ bool detect_group(const int32_t* __restrict__ colidx,
       past = true;
     }
     if (__ballot(conf) & gmask) return true;
-    if (SORTED && (__ballot(past) & gmask)) return false;
+    if (sorted && (__ballot(past) & gmask)) return false;
   }
   return false;
 }
@@ -149,8 +153,8 @@ struct HeavySmem {
   int lost;
 };
 
-template <typename RP>
-__device__ int spec_block(const int32_t* __restrict__ colidx, const int32_t* __restrict__ st,
+template <typename RP, typename S>
+__device__ int spec_block(const int32_t* __restrict__ colidx, const S* __restrict__ st,
                           RP b, RP e, HeavySmem& sm) {
   const int tid = threadIdx.x;
   int base = 0;
@@ -200,9 +204,9 @@ __device__ int spec_block(const int32_t* __restrict__ colidx, const int32_t* __r
   }
 }
 
-template <typename RP, bool SORTED>
-__device__ bool detect_block(const int32_t* __restrict__ colidx, const int32_t* __restrict__ st,
-                             RP b, RP e, int v, int t) {
+template <typename RP, typename S>
+__device__ bool detect_block(const int32_t* __restrict__ colidx, const S* __restrict__ st,
+                             RP b, RP e, int v, int t, bool sorted) {
   const int tid = threadIdx.x;
   for (RP kb = b; kb < e; kb += kBlock) {
     RP k = kb + tid;
@@ -215,7 +219,7 @@ __device__ bool detect_block(const int32_t* __restrict__ colidx, const int32_t* 
       past = 1;
     }
     if (__syncthreads_or(conf)) return true;
-    if (SORTED && __syncthreads_or(past)) return false;
+    if (sorted && __syncthreads_or(past)) return false;
   }
   return false;
 }
@@ -228,7 +232,7 @@ struct Tally {
   int lost;    // of which lost (detect only)
 };
 
-template <typename RP, int L, int PHASE, bool SORTED>
+template <typename RP, typename S, int L, int PHASE>
 __device__ void light_phase(const KArgs& a, long wave_gid, long nwaves, Tally& tl) {
   const int lane = lane_id();
   const int gl = lane & (L - 1);
@@ -236,6 +240,8 @@ __device__ void light_phase(const KArgs& a, long wave_gid, long nwaves, Tally& t
   constexpr int G = kWave / L;
   const uint64_t gmask = (L == kWave) ? ~0ull : (((1ull << L) - 1) << (grp * L));
   const RP* __restrict__ rp = (const RP*)a.rowptr;
+  S* __restrict__ st = (S*)a.st;
+  const bool sorted = a.sorted != 0;
   const long nchunks = ((long)a.n + kWave - 1) / kWave;
   for (long ch = wave_gid; ch < nchunks; ch += nwaves) {
     const int v = (int)(ch * kWave) + lane;
@@ -243,7 +249,7 @@ __device__ void light_phase(const KArgs& a, long wave_gid, long nwaves, Tally& t
     int s = 0;
     RP b = 0, e = 0;
     if (v < a.n) {
-      s = a.st[v];
+      s = st[v];
       if (s < 0) {
         b = rp[v];
         e = rp[v + 1];
@@ -263,13 +269,13 @@ __device__ void light_phase(const KArgs& a, long wave_gid, long nwaves, Tally& t
       const int vv = (int)(ch * kWave) + pos;
       if (valid) {  // group-uniform
         if (PHASE == kSpec) {
-          int t = spec_group<RP, L>(a.colidx, a.st, vb, ve, gl);
-          if (gl == 0) a.st[vv] = ~t;
+          int t = spec_group<RP, S, L>(a.colidx, st, vb, ve, gl);
+          if (gl == 0) st[vv] = (S)~t;
         } else {
           const int t = ~vs;
-          bool lose = detect_group<RP, L, SORTED>(a.colidx, a.st, vb, ve, vv, t, gl, gmask);
+          bool lose = detect_group<RP, S, L>(a.colidx, st, vb, ve, vv, t, gl, gmask, sorted);
           if (gl == 0) {
-            if (!lose) a.st[vv] = t;
+            if (!lose) st[vv] = (S)t;
             tl.lost += lose;
           }
         }
@@ -279,23 +285,24 @@ __device__ void light_phase(const KArgs& a, long wave_gid, long nwaves, Tally& t
   }
 }
 
-template <typename RP, int PHASE, bool SORTED>
+template <typename RP, typename S, int PHASE>
 __device__ void medium_phase(const KArgs& a, long wave_gid, long nwaves, Tally& tl) {
   const int lane = lane_id();
   const RP* __restrict__ rp = (const RP*)a.rowptr;
+  S* __restrict__ st = (S*)a.st;
   for (long i = wave_gid; i < a.mcount; i += nwaves) {
     const int v = a.mlist[i];
-    const int s = a.st[v];
+    const int s = st[v];
     if (s >= 0) continue;  // wave-uniform
     const RP b = rp[v], e = rp[v + 1];
     if (PHASE == kSpec) {
-      int t = spec_group<RP, kWave>(a.colidx, a.st, b, e, lane);
-      if (lane == 0) a.st[v] = ~t;
+      int t = spec_group<RP, S, kWave>(a.colidx, st, b, e, lane);
+      if (lane == 0) st[v] = (S)~t;
     } else {
       const int t = ~s;
-      bool lose = detect_group<RP, kWave, SORTED>(a.colidx, a.st, b, e, v, t, lane, ~0ull);
+      bool lose = detect_group<RP, S, kWave>(a.colidx, st, b, e, v, t, lane, ~0ull, a.sorted != 0);
       if (lane == 0) {
-        if (!lose) a.st[v] = t;
+        if (!lose) st[v] = (S)t;
         tl.lost += lose;
       }
     }
@@ -303,23 +310,24 @@ __device__ void medium_phase(const KArgs& a, long wave_gid, long nwaves, Tally& 
   }
 }
 
-template <typename RP, int PHASE, bool SORTED>
+template <typename RP, typename S, int PHASE>
 __device__ void heavy_phase(const KArgs& a, long blk, long nblk, Tally& tl, HeavySmem& sm) {
   const RP* __restrict__ rp = (const RP*)a.rowptr;
+  S* __restrict__ st = (S*)a.st;
   for (long i = blk; i < a.hcount; i += nblk) {
     const int v = a.hlist[i];
-    const int s = a.st[v];
+    const int s = st[v];
     __syncthreads();  // the commit below happens after every thread read s
     if (s >= 0) continue;  // block-uniform
     const RP b = rp[v], e = rp[v + 1];
     if (PHASE == kSpec) {
-      int t = spec_block<RP>(a.colidx, a.st, b, e, sm);
-      if (threadIdx.x == 0) a.st[v] = ~t;
+      int t = spec_block<RP, S>(a.colidx, st, b, e, sm);
+      if (threadIdx.x == 0) st[v] = (S)~t;
     } else {
       const int t = ~s;
-      bool lose = detect_block<RP, SORTED>(a.colidx, a.st, b, e, v, t);
+      bool lose = detect_block<RP, S>(a.colidx, st, b, e, v, t, a.sorted != 0);
       if (threadIdx.x == 0) {
-        if (!lose) a.st[v] = t;
+        if (!lose) st[v] = (S)t;
         tl.lost += lose;
       }
     }
@@ -327,42 +335,45 @@ __device__ void heavy_phase(const KArgs& a, long blk, long nblk, Tally& tl, Heav
   }
 }
 
-// A whole phase of round r over every uncoloured vertex, by one block of a
-// grid of nblk blocks.  Detect also publishes whether round r + 1 has work
-// (more[(r+1) % 3]), clears more[(r+2) % 3] for the round after, and records
-// r as the last non-empty round and |U_r| in the trace.
-template <typename RP, int L, int PHASE, bool SORTED>
-__device__ void phase(const KArgs& a, int r, long blk, long nblk, HeavySmem& sm) {
-  Tally tl{0, 0};
-  if (PHASE == kDetect && blk == 0 && threadIdx.x == 0) a.ctrl->more[(r + 2) % 3].v = 0;
-  heavy_phase<RP, PHASE, SORTED>(a, blk, nblk, tl, sm);
-  const long wave_gid = blk * kWavesPerBlock + threadIdx.x / kWave;
-  const long nwaves = nblk * kWavesPerBlock;
-  medium_phase<RP, PHASE, SORTED>(a, wave_gid, nwaves, tl);
-  light_phase<RP, L, PHASE, SORTED>(a, wave_gid, nwaves, tl);
-  if (PHASE == kDetect) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      sm.active = 0;
-      sm.lost = 0;
-    }
-    __syncthreads();
-    if (tl.active) atomicAdd(&sm.active, tl.active);
-    if (tl.lost) atomicAdd(&sm.lost, tl.lost);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      if (sm.lost) a.ctrl->more[(r + 1) % 3].v = 1;
-      if (sm.active) {
-        a.ctrl->last_round.v = r;
-        if (r - 1 < kTraceRounds) atomicAdd(&a.ctrl->trace[r - 1], sm.active);
-      }
+// Detect publishes, per block: whether round r + 1 has work
+// (more[(r+1) % 3]), r as the last non-empty round, and |U_r| in the trace.
+__device__ void publish_detect(const KArgs& a, int r, const Tally& tl, HeavySmem& sm) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    sm.active = 0;
+    sm.lost = 0;
+  }
+  __syncthreads();
+  if (tl.active) atomicAdd(&sm.active, tl.active);
+  if (tl.lost) atomicAdd(&sm.lost, tl.lost);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (sm.lost) a.ctrl->more[(r + 1) % 3].v = 1;
+    if (sm.active) {
+      a.ctrl->last_round.v = r;
+      if (r - 1 < kTraceRounds) atomicAdd(&a.ctrl->trace[r - 1], sm.active);
     }
   }
 }
 
+// A whole phase of round r over every uncoloured vertex, by one block of a
+// grid of nblk blocks.  Detect also clears more[(r+2) % 3] for the round
+// after next.
+template <typename RP, typename S, int L, int PHASE>
+__device__ void phase(const KArgs& a, int r, long blk, long nblk, HeavySmem& sm) {
+  Tally tl{0, 0};
+  if (PHASE == kDetect && blk == 0 && threadIdx.x == 0) a.ctrl->more[(r + 2) % 3].v = 0;
+  heavy_phase<RP, S, PHASE>(a, blk, nblk, tl, sm);
+  const long wave_gid = blk * kWavesPerBlock + threadIdx.x / kWave;
+  const long nwaves = nblk * kWavesPerBlock;
+  medium_phase<RP, S, PHASE>(a, wave_gid, nwaves, tl);
+  light_phase<RP, S, L, PHASE>(a, wave_gid, nwaves, tl);
+  if (PHASE == kDetect) publish_detect(a, r, tl, sm);
+}
+
 // ------------------------------------------------------------- kernels --
 
-template <typename RP, int L, int PHASE, bool SORTED>
+template <typename RP, typename S, int L, int PHASE>
 __global__ __launch_bounds__(kBlock) void k_phase(KArgs a, int round, int from_base) {
   __shared__ HeavySmem sm;
   const int r = from_base ? a.ctrl->round_base.v + round : round;
@@ -370,13 +381,45 @@ __global__ __launch_bounds__(kBlock) void k_phase(KArgs a, int round, int from_b
     if (PHASE == kDetect && blockIdx.x == 0 && threadIdx.x == 0) a.ctrl->more[(r + 2) % 3].v = 0;
     return;
   }
-  phase<RP, L, PHASE, SORTED>(a, r, blockIdx.x, gridDim.x, sm);
+  phase<RP, S, L, PHASE>(a, r, blockIdx.x, gridDim.x, sm);
+}
+
+// Round 1 in closed form for sorted rows: nothing is final, so every vertex
+// tries colour 0 and v keeps it exactly when no neighbour has a lower id,
+// i.e. when its first (smallest) neighbour is above v.  One lane per vertex
+// writes the whole state array, so no initialisation pass is needed.
+template <typename RP, typename S>
+__global__ __launch_bounds__(kBlock) void k_round1_sorted(KArgs a) {
+  __shared__ HeavySmem sm;
+  const RP* __restrict__ rp = (const RP*)a.rowptr;
+  S* __restrict__ st = (S*)a.st;
+  Tally tl{0, 0};
+  const long tid = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const long nth = (long)gridDim.x * blockDim.x;
+  for (long v = tid; v < a.n; v += nth) {
+    const RP b = rp[v], e = rp[v + 1];
+    const bool lose = e > b && a.colidx[b] < v;
+    st[v] = lose ? (S)-1 : (S)0;
+    tl.lost += lose;
+    tl.active += 1;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.ctrl->more[0].v = 0;  // (1 + 2) % 3
+  publish_detect(a, 1, tl, sm);
+}
+
+// Unsorted rows: initialise every vertex to "tentative 0"; the general
+// detect phase then runs round 1.
+template <typename S>
+__global__ void k_fill_tent0(KArgs a) {
+  S* __restrict__ st = (S*)a.st;
+  const long tid = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const long nth = (long)gridDim.x * blockDim.x;
+  for (long v = tid; v < a.n; v += nth) st[v] = (S)-1;
 }
 
 __global__ void k_init(KArgs a) {
   const long tid = blockIdx.x * (long)blockDim.x + threadIdx.x;
   const long nth = (long)gridDim.x * blockDim.x;
-  for (long v = tid; v < a.n; v += nth) a.st[v] = -1;  // tentative colour 0
   for (long i = tid; i < kTraceRounds; i += nth) a.ctrl->trace[i] = 0;
   if (tid == 0) {
     a.ctrl->more[0].v = 0;
@@ -395,6 +438,9 @@ __global__ void k_advance_base(Ctrl* c, int by) {
   if (threadIdx.x == 0 && blockIdx.x == 0) c->round_base.v += by;
 }
 
+// Colour count, uncoloured count, and the widening of a narrow state into
+// the caller's int32 colours.
+template <typename S>
 __global__ __launch_bounds__(kBlock) void k_finish(KArgs a) {
   __shared__ int sh_max, sh_left;
   if (threadIdx.x == 0) {
@@ -402,11 +448,13 @@ __global__ __launch_bounds__(kBlock) void k_finish(KArgs a) {
     sh_left = 0;
   }
   __syncthreads();
+  const S* __restrict__ st = (const S*)a.st;
   int mx = -1, left = 0;
   const long tid = blockIdx.x * (long)blockDim.x + threadIdx.x;
   const long nth = (long)gridDim.x * blockDim.x;
   for (long v = tid; v < a.n; v += nth) {
-    int s = a.st[v];
+    const int s = st[v];
+    a.colors[v] = s;
     mx = s > mx ? s : mx;
     left += s < 0;
   }
@@ -451,21 +499,29 @@ __device__ __forceinline__ bool grid_barrier(Ctrl* c, unsigned& epoch) {
   return sh_abort == 0;
 }
 
-// The whole colouring in one launch: round 1 (detect only), then rounds of
-// speculate / barrier / detect / barrier until a round has no losers.
-template <typename RP, int L, bool SORTED>
+// The whole colouring in one launch: round 1 (detect only, from the state
+// -1 everywhere), then rounds of speculate / barrier / detect / barrier until
+// a round has no losers.
+template <typename RP, typename S, int L>
 __global__ __launch_bounds__(kBlock) void k_persistent(KArgs a, int max_rounds) {
   __shared__ HeavySmem sm;
   unsigned epoch = 0;
-  phase<RP, L, kDetect, SORTED>(a, 1, blockIdx.x, gridDim.x, sm);
+  {
+    S* __restrict__ st = (S*)a.st;
+    const long tid = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    const long nth = (long)gridDim.x * blockDim.x;
+    for (long v = tid; v < a.n; v += nth) st[v] = (S)-1;
+  }
+  if (!grid_barrier(a.ctrl, epoch)) return;
+  phase<RP, S, L, kDetect>(a, 1, blockIdx.x, gridDim.x, sm);
   if (!grid_barrier(a.ctrl, epoch)) return;
   for (int r = 2; max_rounds <= 0 || r <= max_rounds; ++r) {
     const int more = __hip_atomic_load(&a.ctrl->more[r % 3].v, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
     if (!more) break;  // grid-uniform: read after a barrier, written before it
-    phase<RP, L, kSpec, SORTED>(a, r, blockIdx.x, gridDim.x, sm);
+    phase<RP, S, L, kSpec>(a, r, blockIdx.x, gridDim.x, sm);
     if (!grid_barrier(a.ctrl, epoch)) return;
-    phase<RP, L, kDetect, SORTED>(a, r, blockIdx.x, gridDim.x, sm);
+    phase<RP, S, L, kDetect>(a, r, blockIdx.x, gridDim.x, sm);
     if (!grid_barrier(a.ctrl, epoch)) return;
   }
 }
@@ -557,81 +613,99 @@ __global__ void k_validate(const RP* rowptr, const int32_t* colidx, int32_t n, i
 
 // ------------------------------------------------------ host launchers --
 
-template <typename RP, int L, bool SORTED>
+template <typename RP, typename S, int L>
 static int launch_round_t(const KArgs& a, int phase_id, int round, bool from_base, int grid,
                           hipStream_t s) {
   if (phase_id == kSpec)
-    hipLaunchKernelGGL((k_phase<RP, L, kSpec, SORTED>), dim3(grid), dim3(kBlock), 0, s, a, round,
+    hipLaunchKernelGGL((k_phase<RP, S, L, kSpec>), dim3(grid), dim3(kBlock), 0, s, a, round,
                        (int)from_base);
   else
-    hipLaunchKernelGGL((k_phase<RP, L, kDetect, SORTED>), dim3(grid), dim3(kBlock), 0, s, a,
-                       round, (int)from_base);
+    hipLaunchKernelGGL((k_phase<RP, S, L, kDetect>), dim3(grid), dim3(kBlock), 0, s, a, round,
+                       (int)from_base);
   return (int)hipGetLastError();
 }
 
-template <typename RP, int L, bool SORTED>
+template <typename RP, typename S, int L>
+static int launch_round1_t(const KArgs& a, int grid, hipStream_t s) {
+  if (a.sorted) {
+    hipLaunchKernelGGL((k_round1_sorted<RP, S>), dim3(grid), dim3(kBlock), 0, s, a);
+    return (int)hipGetLastError();
+  }
+  hipLaunchKernelGGL((k_fill_tent0<S>), dim3(grid), dim3(kBlock), 0, s, a);
+  int rc = (int)hipGetLastError();
+  if (rc) return rc;
+  return launch_round_t<RP, S, L>(a, kDetect, 1, false, grid, s);
+}
+
+template <typename RP, typename S, int L>
 static int launch_persistent_t(const KArgs& a, int max_rounds, int grid, hipStream_t s) {
   KArgs aa = a;
   int mr = max_rounds;
   void* args[] = {&aa, &mr};
-  return (int)hipLaunchCooperativeKernel((const void*)&k_persistent<RP, L, SORTED>, dim3(grid),
+  return (int)hipLaunchCooperativeKernel((const void*)&k_persistent<RP, S, L>, dim3(grid),
                                          dim3(kBlock), args, 0, s);
 }
 
-template <typename RP, int L, bool SORTED>
+template <typename RP, typename S, int L>
 static int persistent_grid_t(int* grid_out) {
   int dev = 0, per_cu = 0, cus = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return (int)e;
   e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return (int)e;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)&k_persistent<RP, L, SORTED>,
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)&k_persistent<RP, S, L>,
                                                    kBlock, 0);
   if (e != hipSuccess) return (int)e;
   *grid_out = per_cu * cus;
   return 0;
 }
 
-// Dispatch on (rowptr width, lanes, sorted rows) to the template instances.
-#define GC_DISPATCH_L(RP, SORTED, FN, ...)             \
-  switch (lanes) {                                     \
-    case 1: return FN<RP, 1, SORTED>(__VA_ARGS__);     \
-    case 2: return FN<RP, 2, SORTED>(__VA_ARGS__);     \
-    case 4: return FN<RP, 4, SORTED>(__VA_ARGS__);     \
-    case 8: return FN<RP, 8, SORTED>(__VA_ARGS__);     \
-    case 16: return FN<RP, 16, SORTED>(__VA_ARGS__);   \
-    case 32: return FN<RP, 32, SORTED>(__VA_ARGS__);   \
-    case 64: return FN<RP, 64, SORTED>(__VA_ARGS__);   \
-    default: return (int)hipErrorInvalidValue;         \
+// Dispatch on (rowptr width, state width, lanes) to the template instances.
+#define GC_DISPATCH_L(RP, S, FN, ...)                \
+  switch (lanes) {                                   \
+    case 2: return FN<RP, S, 2>(__VA_ARGS__);        \
+    case 4: return FN<RP, S, 4>(__VA_ARGS__);        \
+    case 8: return FN<RP, S, 8>(__VA_ARGS__);        \
+    case 16: return FN<RP, S, 16>(__VA_ARGS__);      \
+    case 32: return FN<RP, S, 32>(__VA_ARGS__);      \
+    case 64: return FN<RP, S, 64>(__VA_ARGS__);      \
+    default: return (int)hipErrorInvalidValue;       \
   }
 
-#define GC_DISPATCH(FN, ...)                                            \
-  do {                                                                  \
-    if (rp64) {                                                         \
-      if (sorted) { GC_DISPATCH_L(int64_t, true, FN, __VA_ARGS__) }     \
-      else { GC_DISPATCH_L(int64_t, false, FN, __VA_ARGS__) }           \
-    } else {                                                            \
-      if (sorted) { GC_DISPATCH_L(int32_t, true, FN, __VA_ARGS__) }     \
-      else { GC_DISPATCH_L(int32_t, false, FN, __VA_ARGS__) }           \
-    }                                                                   \
+#define GC_DISPATCH_S(RP, FN, ...)                                        \
+  switch (sbytes) {                                                       \
+    case 1: { GC_DISPATCH_L(RP, int8_t, FN, __VA_ARGS__) }                \
+    case 2: { GC_DISPATCH_L(RP, int16_t, FN, __VA_ARGS__) }               \
+    case 4: { GC_DISPATCH_L(RP, int32_t, FN, __VA_ARGS__) }               \
+    default: return (int)hipErrorInvalidValue;                            \
+  }
+
+#define GC_DISPATCH(FN, ...)                                        \
+  do {                                                              \
+    if (rp64) { GC_DISPATCH_S(int64_t, FN, __VA_ARGS__) }           \
+    else { GC_DISPATCH_S(int32_t, FN, __VA_ARGS__) }                \
   } while (0)
 
-int launch_round(const KArgs& a, bool rp64, bool sorted, int lanes, int phase_id, int round,
+int launch_round(const KArgs& a, bool rp64, int sbytes, int lanes, int phase_id, int round,
                  bool round_from_base, int grid, void* stream) {
   GC_DISPATCH(launch_round_t, a, phase_id, round, round_from_base, grid, (hipStream_t)stream);
 }
 
-int launch_persistent(const KArgs& a, bool rp64, bool sorted, int lanes, int max_rounds, int grid,
+int launch_round1(const KArgs& a, bool rp64, int sbytes, int lanes, int grid, void* stream) {
+  GC_DISPATCH(launch_round1_t, a, grid, (hipStream_t)stream);
+}
+
+int launch_persistent(const KArgs& a, bool rp64, int sbytes, int lanes, int max_rounds, int grid,
                       void* stream) {
   GC_DISPATCH(launch_persistent_t, a, max_rounds, grid, (hipStream_t)stream);
 }
 
-int persistent_max_grid(bool rp64, bool sorted, int lanes, int* grid_out) {
+int persistent_max_grid(bool rp64, int sbytes, int lanes, int* grid_out) {
   GC_DISPATCH(persistent_grid_t, grid_out);
 }
 
-int launch_init(const KArgs& a, void* stream, int grid) {
-  hipLaunchKernelGGL(k_init, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, a);
+int launch_init(const KArgs& a, void* stream) {
+  hipLaunchKernelGGL(k_init, dim3(64), dim3(kBlock), 0, (hipStream_t)stream, a);
   return (int)hipGetLastError();
 }
 
@@ -640,8 +714,14 @@ int launch_advance_base(const KArgs& a, int by, void* stream) {
   return (int)hipGetLastError();
 }
 
-int launch_finish(const KArgs& a, int grid, void* stream) {
-  hipLaunchKernelGGL(k_finish, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, a);
+int launch_finish(const KArgs& a, int sbytes, int grid, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  switch (sbytes) {
+    case 1: hipLaunchKernelGGL(k_finish<int8_t>, dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(k_finish<int16_t>, dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 4: hipLaunchKernelGGL(k_finish<int32_t>, dim3(grid), dim3(kBlock), 0, s, a); break;
+    default: return (int)hipErrorInvalidValue;
+  }
   return (int)hipGetLastError();
 }
 
