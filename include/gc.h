@@ -56,7 +56,7 @@ enum gc_status {
   GC_ENOMEM = -2,  /* device or pinned-host allocation failed              */
   GC_EDEVICE = -3, /* HIP runtime error or GPU fault                       */
   GC_EROUNDS = -4, /* round cap (GC_OPT_MAX_ROUNDS) reached before the end */
-  GC_EBUSY = -5,   /* handle already in use by an unfinished call          */
+  GC_EBUSY = -5,   /* reserved (calls on a handle are ordered instead)     */
   GC_ETOOBIG = -6  /* sizes exceed what the library supports               */
 };
 
@@ -147,8 +147,13 @@ enum gc_option {
   GC_OPT_HEAVY_COUNT = 10,   /* (get only) vertices on the workgroup path           */
   GC_OPT_PERSISTENT_BLOCKS_PER_CU = 11, /* workgroups per CU of the persistent kernel,
                                 1..6 (4); more are not reliably co-resident   */
-  GC_OPT_STATE_BYTES = 12    /* (get only) bytes per vertex of the working state:
+  GC_OPT_STATE_BYTES = 12,   /* (get only) bytes per vertex of the working state:
                                 1 if max degree <= 127, 2 if <= 32767, else 4 */
+  GC_OPT_PROFILE = 13        /* 1: time the kernels of each call with HIP events
+                                recorded on the call's stream; once R is known
+                                the rounds are launched directly (not as a
+                                captured graph) with an event around every
+                                kernel; read with gc_get_profile           */
 };
 enum gc_mode {
   GC_MODE_AUTO = 0,       /* currently GRAPH                                      */
@@ -159,6 +164,18 @@ enum gc_mode {
 };
 int gc_set_option(gc_handle h, int option, int64_t value);
 int gc_get_option(gc_handle h, int option, int64_t *value);
+
+/*
+ * gc_get_profile -- kernel times accumulated over profiled calls
+ * (GC_OPT_PROFILE = 1), per kernel kind: [0] round 1, [1] speculate,
+ * [2] detect/commit, [3] finish (colour count and widening).  `ms` (4
+ * doubles) receives total milliseconds, `launches` (4 int64) the launch
+ * counts; either may be NULL.  Speculate and detect are timed once the round
+ * count is known (calls still discovering R, and persistent calls, add only
+ * round 1 and finish).  Waits for the handle's last call.  reset != 0 zeroes
+ * the totals after reading.
+ */
+int gc_get_profile(gc_handle h, double *ms, int64_t *launches, int reset);
 
 /* gc_destroy -- wait for outstanding work, free the handle's scratch.
  * The borrowed graph arrays are not touched.  NULL is accepted. */

@@ -52,6 +52,9 @@ struct Captured {  // one instantiated chunk of K rounds
   int k = 0, lanes = 0, light = 0;
 };
 
+// Kernel kinds reported by gc_get_profile.
+enum { kRound1 = 0, kSpecK = 1, kDetectK = 2, kFinishK = 3, kKinds = 4 };
+
 }  // namespace
 
 struct gc_ctx {
@@ -91,6 +94,16 @@ struct gc_ctx {
 
   Captured chunk;  // discovery chunk (chunk_rounds)
   Captured exact;  // R - 1 rounds, once R is known
+
+  // profiling (GC_OPT_PROFILE): events around the kernels of a call
+  bool profile = false;
+  hipEvent_t pev[4] = {nullptr, nullptr, nullptr, nullptr};  // round 1 start/end, finish start/end
+  hipEvent_t* rev = nullptr;  // 3 per round of rounds 2..R: spec start, spec end, detect end
+  int rev_rounds = 0;         // rounds rev has room for
+  int timed_rounds = 0;       // rounds 2..R timed by the last call
+  bool pending_profile = false;
+  double prof_ms[kKinds] = {0, 0, 0, 0};
+  int64_t prof_launches[kKinds] = {0, 0, 0, 0};
 
   std::string err;
 };
@@ -187,6 +200,10 @@ static void free_ctx(gc_ctx* h) {
   if (!h) return;
   drop(h->chunk);
   drop(h->exact);
+  for (hipEvent_t& e : h->pev)
+    if (e) (void)hipEventDestroy(e);
+  for (int i = 0; i < 3 * h->rev_rounds; ++i) (void)hipEventDestroy(h->rev[i]);
+  delete[] h->rev;
   if (h->done) (void)hipEventDestroy(h->done);
   if (h->ctrl) (void)hipFree(h->ctrl);
   if (h->state) (void)hipFree(h->state);
@@ -278,11 +295,10 @@ extern "C" int gc_create(gc_handle* out, const void* rowptr, const int32_t* coli
   return GC_OK;
 }
 
+// Wait on the host for the handle's last call (option changes and teardown).
 static int ensure_idle(gc_ctx* h) {
   if (!h->in_flight) return GC_OK;
-  hipError_t q = hipEventQuery(h->done);
-  if (q == hipErrorNotReady) return set_err(h, GC_EBUSY, "handle busy: previous gc_color not finished");
-  if (q != hipSuccess) return set_err(h, GC_EDEVICE, "previous call failed: %s", hipGetErrorString(q));
+  HIPCHECK(h, hipEventSynchronize(h->done));
   h->in_flight = false;
   return GC_OK;
 }
@@ -316,6 +332,7 @@ static int capture(gc_ctx* h, Captured& c, const KArgs& a, int L, int K) {
   (void)hipStreamDestroy(cs);
   if (rc || e2 != hipSuccess) {
     if (g) (void)hipGraphDestroy(g);
+    drop(c);
     return set_err(h, GC_EDEVICE, "capture failed: %s",
                    hipGetErrorString(rc ? (hipError_t)rc : e2));
   }
@@ -323,6 +340,7 @@ static int capture(gc_ctx* h, Captured& c, const KArgs& a, int L, int K) {
   e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
   if (e != hipSuccess) {
     (void)hipGraphDestroy(g);
+    drop(c);
     return set_err(h, GC_EDEVICE, "instantiate: %s", hipGetErrorString(e));
   }
   c.graph = g;
@@ -337,19 +355,75 @@ static bool usable(const Captured& c, int K, int L, int light) {
   return c.exec && c.k == K && c.lanes == L && c.light == light;
 }
 
+static float elapsed(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+    (void)hipGetLastError();  // do not leave the failure for a later launch check
+    return 0.f;
+  }
+  return ms;
+}
+
+// Room for per-round events of `rounds` rounds.
+static int reserve_round_events(gc_ctx* h, int rounds) {
+  if (rounds <= h->rev_rounds) return GC_OK;
+  hipEvent_t* ev = new (std::nothrow) hipEvent_t[3 * (size_t)rounds]();
+  if (!ev) return set_err(h, GC_ENOMEM, "profile events: host memory");
+  for (int i = 0; i < 3 * h->rev_rounds; ++i) ev[i] = h->rev[i];
+  for (int i = 3 * h->rev_rounds; i < 3 * rounds; ++i) {
+    if (hipEventCreate(&ev[i]) != hipSuccess) {
+      for (int j = 3 * h->rev_rounds; j < i; ++j) (void)hipEventDestroy(ev[j]);
+      delete[] ev;
+      return set_err(h, GC_EDEVICE, "profile events: hipEventCreate failed");
+    }
+  }
+  delete[] h->rev;
+  h->rev = ev;
+  h->rev_rounds = rounds;
+  return GC_OK;
+}
+
+// Add the kernel times of the finished last call to the profile totals.
+static void collect_profile(gc_ctx* h) {
+  if (!h->pending_profile) return;
+  h->pending_profile = false;
+  h->prof_ms[kRound1] += elapsed(h->pev[0], h->pev[1]);
+  h->prof_launches[kRound1] += 1;
+  h->prof_ms[kFinishK] += elapsed(h->pev[2], h->pev[3]);
+  h->prof_launches[kFinishK] += 1;
+  for (int j = 0; j < h->timed_rounds; ++j) {
+    h->prof_ms[kSpecK] += elapsed(h->rev[3 * j], h->rev[3 * j + 1]);
+    h->prof_ms[kDetectK] += elapsed(h->rev[3 * j + 1], h->rev[3 * j + 2]);
+  }
+  h->prof_launches[kSpecK] += h->timed_rounds;
+  h->prof_launches[kDetectK] += h->timed_rounds;
+  h->timed_rounds = 0;
+}
+
 extern "C" int gc_color(gc_handle h, int32_t* colors_out, void* stream) {
   if (!h) return set_err(nullptr, GC_EINVAL, "gc_color: NULL handle");
   if (h->n > 0 && !colors_out) return set_err(h, GC_EINVAL, "gc_color: colors_out is NULL");
-  int rc = ensure_idle(h);
-  if (rc) return rc;
+  int rc = GC_OK;
   int cur = 0;
   HIPCHECK(h, hipGetDevice(&cur));
   if (cur != h->device) HIPCHECK(h, hipSetDevice(h->device));
   hipStream_t s = (hipStream_t)stream;
+  // Calls on one handle are ordered: a call waits (on the device) for the
+  // previous one, whose scratch it reuses.  A profiled call's events are
+  // read before they are recorded again.
+  if (h->in_flight && h->pending_profile) {
+    rc = ensure_idle(h);
+    if (rc) return rc;
+    collect_profile(h);
+  }
+  if (h->in_flight) HIPCHECK(h, hipStreamWaitEvent(s, h->done, 0));
   if (h->lists_dirty) {
+    rc = ensure_idle(h);
+    if (rc) return rc;
     rc = classify(h, s);
     if (rc) return rc;
   }
+  (void)hipGetLastError();  // launch checks below must see only this call's errors
   h->stats_ready = false;
   const int L = auto_lanes(h);
   const int light = light_max_of(h, L);
@@ -368,9 +442,25 @@ extern "C" int gc_color(gc_handle h, int32_t* colors_out, void* stream) {
     if (pg < 1) return set_err(h, GC_EDEVICE, "persistent kernel cannot be resident");
     LCHECK(h, gc::launch_persistent(a, h->rp64, h->sbytes, L, h->max_rounds, pg, s));
   } else {
+    if (h->profile) HIPCHECK(h, hipEventRecord(h->pev[0], s));
     LCHECK(h, gc::launch_round1(a, h->rp64, h->sbytes, L, grid, s));
+    if (h->profile) HIPCHECK(h, hipEventRecord(h->pev[1], s));
     int r = 1;  // last round queued
-    if (mode == GC_MODE_GRAPH && h->known_rounds > 0) {
+    if (h->profile && h->known_rounds > 0) {
+      // Profiled call with R known: rounds 2..R launched directly, each kernel
+      // between two events on the caller's stream.
+      const int K = (int)h->known_rounds - 1;
+      rc = reserve_round_events(h, K);
+      if (rc) return rc;
+      for (int j = 0; j < K; ++j) {
+        HIPCHECK(h, hipEventRecord(h->rev[3 * j], s));
+        LCHECK(h, gc::launch_round(a, h->rp64, h->sbytes, L, 0, 2 + j, false, grid, s));
+        HIPCHECK(h, hipEventRecord(h->rev[3 * j + 1], s));
+        LCHECK(h, gc::launch_round(a, h->rp64, h->sbytes, L, 1, 2 + j, false, grid, s));
+        HIPCHECK(h, hipEventRecord(h->rev[3 * j + 2], s));
+      }
+      h->timed_rounds = K;
+    } else if (mode == GC_MODE_GRAPH && h->known_rounds > 0) {
       // R is known: queue rounds 2..R in one captured chunk, no read-back.
       const int K = (int)h->known_rounds - 1;
       if (K > 0) {
@@ -413,7 +503,10 @@ extern "C" int gc_color(gc_handle h, int32_t* colors_out, void* stream) {
       }
     }
   }
+  if (h->profile) HIPCHECK(h, hipEventRecord(h->pev[2], s));
   LCHECK(h, gc::launch_finish(a, h->sbytes, std::min(grid, 1024), s));
+  if (h->profile) HIPCHECK(h, hipEventRecord(h->pev[3], s));
+  h->pending_profile = h->profile && mode != GC_MODE_PERSISTENT;
   HIPCHECK(h, hipMemcpyAsync(&h->host->last_round, &h->ctrl->last_round.v, 4, hipMemcpyDeviceToHost, s));
   HIPCHECK(h, hipMemcpyAsync(&h->host->ncolors, &h->ctrl->ncolors.v, 4, hipMemcpyDeviceToHost, s));
   HIPCHECK(h, hipMemcpyAsync(&h->host->abort, &h->ctrl->abort.v, 4, hipMemcpyDeviceToHost, s));
@@ -430,6 +523,7 @@ static int wait_done(gc_ctx* h) {
     HIPCHECK(h, hipEventSynchronize(h->done));
     h->in_flight = false;
   }
+  collect_profile(h);
   if (h->host->abort) return set_err(h, GC_EDEVICE, "persistent kernel: grid barrier timed out");
   if (h->host->left) {
     if (h->max_rounds > 0 && h->host->last_round >= h->max_rounds)
@@ -512,6 +606,13 @@ extern "C" int gc_set_option(gc_handle h, int option, int64_t value) {
       if (value < 1 || value > 6) break;
       h->persist_per_cu = (int)value;
       return GC_OK;
+    case GC_OPT_PROFILE:
+      if (value < 0 || value > 1) break;
+      if (value && !h->pev[0]) {
+        for (hipEvent_t& e : h->pev) HIPCHECK(h, hipEventCreate(&e));
+      }
+      h->profile = value != 0;
+      return GC_OK;
     default:
       return set_err(h, GC_EINVAL, "gc_set_option: unknown option %d", option);
   }
@@ -534,8 +635,25 @@ extern "C" int gc_get_option(gc_handle h, int option, int64_t* value) {
     case GC_OPT_HEAVY_COUNT: *value = h->hcount; return GC_OK;
     case GC_OPT_PERSISTENT_BLOCKS_PER_CU: *value = h->persist_per_cu; return GC_OK;
     case GC_OPT_STATE_BYTES: *value = h->sbytes; return GC_OK;
+    case GC_OPT_PROFILE: *value = h->profile; return GC_OK;
     default: return set_err(h, GC_EINVAL, "gc_get_option: unknown option %d", option);
   }
+}
+
+extern "C" int gc_get_profile(gc_handle h, double* ms, int64_t* launches, int reset) {
+  if (!h) return set_err(nullptr, GC_EINVAL, "gc_get_profile: NULL handle");
+  int rc = ensure_idle(h);
+  if (rc) return rc;
+  collect_profile(h);
+  for (int k = 0; k < kKinds; ++k) {
+    if (ms) ms[k] = h->prof_ms[k];
+    if (launches) launches[k] = h->prof_launches[k];
+    if (reset) {
+      h->prof_ms[k] = 0;
+      h->prof_launches[k] = 0;
+    }
+  }
+  return GC_OK;
 }
 
 extern "C" int gc_destroy(gc_handle h) {

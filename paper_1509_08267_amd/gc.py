@@ -27,7 +27,9 @@ GC_ROWPTR_I64, GC_VALIDATE, GC_ROWS_SORTED = 1, 2, 4
 # enum gc_option
 (GC_OPT_MODE, GC_OPT_LANES, GC_OPT_HEAVY_DEGREE, GC_OPT_BLOCKS_PER_CU, GC_OPT_MAX_ROUNDS,
  GC_OPT_CHUNK_ROUNDS, GC_OPT_MEDIUM_DEGREE, GC_OPT_MAX_DEGREE, GC_OPT_MEDIUM_COUNT,
- GC_OPT_HEAVY_COUNT, GC_OPT_PERSISTENT_BLOCKS_PER_CU, GC_OPT_STATE_BYTES) = range(1, 13)
+ GC_OPT_HEAVY_COUNT, GC_OPT_PERSISTENT_BLOCKS_PER_CU, GC_OPT_STATE_BYTES,
+ GC_OPT_PROFILE) = range(1, 14)
+PROFILE_KINDS = ("round1", "speculate", "detect", "finish")
 # enum gc_mode
 GC_MODE_AUTO, GC_MODE_HOST, GC_MODE_CHUNKED, GC_MODE_PERSISTENT, GC_MODE_GRAPH = range(5)
 MODES = {"auto": GC_MODE_AUTO, "host": GC_MODE_HOST, "chunked": GC_MODE_CHUNKED,
@@ -36,7 +38,8 @@ GC_TRACE_ROUNDS = 65536
 
 # Every symbol the header declares, for the load check.
 EXPORTS = ["gc_create", "gc_color", "gc_get_stats", "gc_get_round_sizes", "gc_set_option",
-           "gc_get_option", "gc_destroy", "gc_last_error", "gc_batch_workspace_bytes",
+           "gc_get_option", "gc_get_profile", "gc_destroy", "gc_last_error",
+           "gc_batch_workspace_bytes",
            "gc_color_batch", "gc_batch_step_workspace_bytes", "gc_batch_step", "gc_version"]
 
 
@@ -72,6 +75,7 @@ def load():
     lib.gc_get_round_sizes.argtypes = [p, p, i64, ctypes.POINTER(i64)]
     lib.gc_set_option.argtypes = [p, ctypes.c_int, i64]
     lib.gc_get_option.argtypes = [p, ctypes.c_int, ctypes.POINTER(i64)]
+    lib.gc_get_profile.argtypes = [p, p, p, ctypes.c_int]
     lib.gc_destroy.argtypes = [p]
     lib.gc_last_error.argtypes = [p]
     lib.gc_last_error.restype = ctypes.c_char_p
@@ -83,7 +87,7 @@ def load():
     lib.gc_batch_step.argtypes = [i64, p, p, p, p, i32, p, sz, p]
     lib.gc_version.restype = ctypes.c_char_p
     for name in ("gc_create", "gc_color", "gc_get_stats", "gc_get_round_sizes", "gc_set_option",
-                 "gc_get_option", "gc_destroy", "gc_color_batch", "gc_batch_step"):
+                 "gc_get_option", "gc_get_profile", "gc_destroy", "gc_color_batch", "gc_batch_step"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -148,6 +152,15 @@ def gc_get_option(h: int, option: int) -> int:
     v = ctypes.c_int64()
     _check(load().gc_get_option(h, option, ctypes.byref(v)), h)
     return int(v.value)
+
+
+def gc_get_profile(h: int, reset: bool = False):
+    """{kind: (total_ms, launches)} for round1, speculate, detect, finish."""
+    import numpy as np
+    ms = np.zeros(4, np.float64)
+    n = np.zeros(4, np.int64)
+    _check(load().gc_get_profile(h, ms.ctypes.data, n.ctypes.data, int(reset)), h)
+    return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(PROFILE_KINDS)}
 
 
 def gc_destroy(h: int) -> None:
@@ -216,7 +229,8 @@ class Graph:
     _OPTS = {"mode": GC_OPT_MODE, "lanes": GC_OPT_LANES, "heavy_degree": GC_OPT_HEAVY_DEGREE,
              "blocks_per_cu": GC_OPT_BLOCKS_PER_CU, "max_rounds": GC_OPT_MAX_ROUNDS,
              "chunk_rounds": GC_OPT_CHUNK_ROUNDS, "medium_degree": GC_OPT_MEDIUM_DEGREE,
-             "persistent_blocks_per_cu": GC_OPT_PERSISTENT_BLOCKS_PER_CU}
+             "persistent_blocks_per_cu": GC_OPT_PERSISTENT_BLOCKS_PER_CU,
+             "profile": GC_OPT_PROFILE}
 
     def set(self, name: str, value):
         if name == "mode" and isinstance(value, str):
@@ -238,6 +252,9 @@ class Graph:
 
     def round_sizes(self):
         return gc_get_round_sizes(self.h)
+
+    def profile(self, reset: bool = False):
+        return gc_get_profile(self.h, reset)
 
     def close(self):
         if getattr(self, "h", None):

@@ -232,6 +232,24 @@ def test_changed_graph_is_reported(gc):
         assert out.cpu().tolist() == [0, 1, 0, 1]
 
 
+def test_profiled_calls(gc):
+    g = graphgen.er(30000, 300000, 12)
+    ref = oracle.rsc(g.rowptr, g.colidx)
+    rp, ci = _dev(g)
+    with gc.Graph(rp, ci, profile=1) as G:
+        for i in range(3):
+            out = G.color()
+            assert G.stats()[0] == ref.rounds
+            assert np.array_equal(out.cpu().numpy(), ref.colors)
+        prof = G.profile(reset=True)
+        # the first call discovers R (round 1 and finish timed only)
+        assert prof["round1"][1] == 3 and prof["finish"][1] == 3
+        assert prof["speculate"][1] == 2 * (ref.rounds - 1)
+        assert prof["detect"][1] == 2 * (ref.rounds - 1)
+        assert all(ms > 0 for ms, _ in prof.values())
+        assert G.profile()["speculate"] == (0.0, 0)
+
+
 def test_star_with_million_leaves(gc):
     # one vertex of degree 10^6 on the workgroup path (and the leaves first)
     for centre in (0, 1_000_000):
