@@ -667,6 +667,10 @@ extern "C" int gc_destroy(gc_handle h) {
   return rc;
 }
 
+namespace gc {
+void set_thread_error(const char* msg) { tl_error = msg; }
+}  // namespace gc
+
 extern "C" const char* gc_last_error(gc_handle h) {
   return h ? h->err.c_str() : tl_error.c_str();
 }

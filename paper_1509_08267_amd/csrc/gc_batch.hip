@@ -1,15 +1,365 @@
-// gc_batch.hip -- batched colouring entry points (filled in below).
+// gc_batch.hip -- many independent graphs coloured in one launch.
+//
+// Each graph is coloured by one workgroup with exactly the rounds of the
+// per-graph path (Algorithm 1 of Section 3.1 with every vertex its own
+// block; the higher id of a conflicting pair is recoloured), so its colours
+// are bit-identical to a gc_color call on it alone.  The batch only changes
+// where the state lives and who runs it:
+//   - a workgroup takes graphs from a device-side queue ordered largest
+//     first (work buckets by log2 of the CSR size: longest-processing-time
+//     order, so the big graphs do not finish last);
+//   - a graph whose state fits the workgroup's LDS slice (n bytes at int8,
+//     2n at int16, by its maximum degree) keeps it there, so every neighbour
+//     colour gather of every round is an LDS read; larger graphs keep an
+//     int32 state in the caller's colour array;
+//   - the rounds are separated by workgroup barriers instead of grid-wide
+//     ones, and each graph stops independently when its round has no loser.
+// The state between rounds is the colour array itself (final colours >= 0,
+// ~t for a vertex still being coloured with tentative colour t) plus the
+// round count, which makes a step of a few rounds resumable: gc_batch_step
+// advances each listed graph by at most max_rounds rounds.
 #include <hip/hip_runtime.h>
 
-#include "gc.h"
+#include <climits>
+#include <cstdint>
 
-extern "C" size_t gc_batch_workspace_bytes(int64_t, const int64_t*, const int64_t*) { return 0; }
-extern "C" int gc_color_batch(int64_t, const int64_t*, const int64_t*, const int32_t*,
-                              const int32_t*, int32_t*, int32_t*, void*, size_t, void*) {
-  return GC_EINVAL;
+#include "gc.h"
+#include "gc_device.h"
+#include "gc_internal.h"
+
+namespace gc {
+
+constexpr int kBatchBlock = 1024;         // threads per graph workgroup
+constexpr int kBatchLds = 64 * 1024;      // LDS state slice per workgroup (bytes)
+constexpr int kBatchWaves = kBatchBlock / kWave;
+constexpr int kBuckets = 64;
+
+struct BatchCtrl {
+  int32_t queue;  // next position in `order`
+  int32_t pad[63];
+};
+
+// workspace: [BatchCtrl][order: G int32][descs: G gc_graph_desc (packed API only)]
+__host__ __device__ inline size_t ws_order_off() { return sizeof(BatchCtrl); }
+__host__ __device__ inline size_t ws_descs_off(int64_t G) {
+  return (ws_order_off() + (size_t)G * sizeof(int32_t) + 255) & ~(size_t)255;
 }
-extern "C" size_t gc_batch_step_workspace_bytes(int64_t, int64_t) { return 0; }
-extern "C" int gc_batch_step(int64_t, gc_graph_desc*, const int32_t*, const int32_t*, int32_t*,
-                             int32_t, void*, size_t, void*) {
-  return GC_EINVAL;
+
+// Descriptors of a packed batch.
+__global__ void k_batch_descs(int64_t G, const int64_t* voff, const int64_t* eoff,
+                              gc_graph_desc* d) {
+  const long tid = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const long nth = (long)gridDim.x * blockDim.x;
+  for (long g = tid; g < G; g += nth) {
+    gc_graph_desc x;
+    x.rowptr_off = voff[g] + g;
+    x.colidx_off = eoff[g];
+    x.color_off = voff[g];
+    x.n = (int32_t)(voff[g + 1] - voff[g]);
+    x.rounds = 0;
+    x.active = 0;
+    x.max_degree = 0;
+    d[g] = x;
+  }
+}
+
+// Largest-first order: one workgroup buckets the graphs by floor(log2(work))
+// (work = CSR entries + vertices) and writes them out bucket by bucket,
+// largest bucket first.  Also resets the work queue.
+__global__ __launch_bounds__(1024) void k_batch_plan(int64_t G, const gc_graph_desc* d,
+                                                     const int32_t* rowptr_base, int32_t* order,
+                                                     BatchCtrl* ctrl) {
+  __shared__ int hist[kBuckets];
+  __shared__ int base[kBuckets];
+  for (int i = threadIdx.x; i < kBuckets; i += blockDim.x) hist[i] = 0;
+  __syncthreads();
+  for (long g = threadIdx.x; g < G; g += blockDim.x) {
+    const gc_graph_desc x = d[g];
+    const int64_t nnz = x.n > 0 ? rowptr_base[x.rowptr_off + x.n] : 0;
+    const uint64_t work = (uint64_t)nnz + (uint64_t)x.n + 1;
+    atomicAdd(&hist[63 - __builtin_clzll(work)], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int b = kBuckets - 1; b >= 0; --b) {
+      base[b] = acc;
+      acc += hist[b];
+    }
+    ctrl->queue = 0;
+  }
+  __syncthreads();
+  for (long g = threadIdx.x; g < G; g += blockDim.x) {
+    const gc_graph_desc x = d[g];
+    const int64_t nnz = x.n > 0 ? rowptr_base[x.rowptr_off + x.n] : 0;
+    const uint64_t work = (uint64_t)nnz + (uint64_t)x.n + 1;
+    order[atomicAdd(&base[63 - __builtin_clzll(work)], 1)] = (int32_t)g;
+  }
+}
+
+struct GraphRun {
+  const int32_t* rp;
+  const int32_t* ci;
+  int32_t* out;  // the graph's colour / state array (int32)
+  int n;
+  int rounds_in;
+  int max_rounds;
+};
+
+// One pass (speculate or detect) of one round over the graph's uncoloured
+// vertices by the whole workgroup: each wavefront walks 64-vertex chunks,
+// ballots the uncoloured ones and hands them to its groups of L lanes.
+template <typename S, int L, bool SPEC>
+__device__ bool graph_pass(const GraphRun& g, S* st) {
+  const int lane = lane_id();
+  const int gl = lane & (L - 1);
+  const int grp = lane / L;
+  constexpr int Gw = kWave / L;
+  const uint64_t gmask = (L == kWave) ? ~0ull : (((1ull << L) - 1) << (grp * L));
+  const int wave = threadIdx.x / kWave;
+  bool lost = false;
+  for (int ch = wave; ch * kWave < g.n; ch += kBatchWaves) {
+    const int v = ch * kWave + lane;
+    bool act = false;
+    int s = 0, b = 0, e = 0;
+    if (v < g.n) {
+      s = st[v];
+      if (s < 0) {
+        b = g.rp[v];
+        e = g.rp[v + 1];
+        act = true;
+      }
+    }
+    const uint64_t am = __ballot(act);
+    if (am == 0) continue;
+    const int cnt = __popcll(am);
+    for (int p = 0; p < cnt; p += Gw) {
+      const int k = p + grp;
+      const bool valid = k < cnt;
+      const int pos = nth_set_bit(am, valid ? k : 0);
+      const int vb = __shfl(b, pos);
+      const int ve = __shfl(e, pos);
+      const int vs = __shfl(s, pos);
+      const int vv = ch * kWave + pos;
+      if (valid) {
+        if (SPEC) {
+          const int t = spec_group<int32_t, S, L>(g.ci, st, vb, ve, gl);
+          if (gl == 0) st[vv] = (S)~t;
+        } else {
+          const int t = ~vs;
+          const bool lose = detect_group<int32_t, S, L>(g.ci, st, vb, ve, vv, t, gl, gmask, true);
+          if (gl == 0) {
+            if (!lose) st[vv] = (S)t;
+            lost |= lose;
+          }
+        }
+      }
+    }
+  }
+  return lost;
+}
+
+// Rounds of one graph until done or max_rounds more rounds have run.
+// Returns the rounds completed; *left receives the vertices still uncoloured.
+template <typename S, int L, bool IN_LDS>
+__device__ int run_graph(const GraphRun& g, S* st, int* left) {
+  __shared__ int sh_cnt;
+  bool any = false;
+  int r = g.rounds_in;
+  if (r == 0) {
+    // round 1 in closed form (sorted rows): v keeps colour 0 iff no neighbour
+    // has a lower id
+    for (int v = threadIdx.x; v < g.n; v += blockDim.x) {
+      const int b = g.rp[v], e = g.rp[v + 1];
+      const bool lose = e > b && g.ci[b] < v;
+      st[v] = lose ? (S)-1 : (S)0;
+      any |= lose;
+    }
+    r = g.n > 0 ? 1 : 0;
+  } else {
+    for (int v = threadIdx.x; v < g.n; v += blockDim.x) {
+      const int s = g.out[v];
+      if (IN_LDS) st[v] = (S)s;
+      any |= s < 0;
+    }
+  }
+  bool more = __syncthreads_or(any);
+  while (more && (g.max_rounds <= 0 || r - g.rounds_in < g.max_rounds)) {
+    ++r;
+    graph_pass<S, L, true>(g, st);
+    __syncthreads();
+    const bool lost = graph_pass<S, L, false>(g, st);
+    more = __syncthreads_or(lost);
+  }
+  if (threadIdx.x == 0) sh_cnt = 0;
+  __syncthreads();
+  int mine = 0;
+  for (int v = threadIdx.x; v < g.n; v += blockDim.x) {
+    const int s = st[v];
+    if (IN_LDS) g.out[v] = s;
+    mine += s < 0;
+  }
+  if (mine) atomicAdd(&sh_cnt, mine);
+  __syncthreads();
+  *left = sh_cnt;
+  __syncthreads();
+  return r;
+}
+
+template <int L>
+__device__ int dispatch_state(const GraphRun& g, int maxdeg, char* smem, int* left) {
+  if (maxdeg <= 127 && g.n <= kBatchLds) return run_graph<int8_t, L, true>(g, (int8_t*)smem, left);
+  if (maxdeg <= 32767 && 2 * g.n <= kBatchLds)
+    return run_graph<int16_t, L, true>(g, (int16_t*)smem, left);
+  if (4 * g.n <= kBatchLds) return run_graph<int32_t, L, true>(g, (int32_t*)smem, left);
+  return run_graph<int32_t, L, false>(g, g.out, left);
+}
+
+__global__ __launch_bounds__(kBatchBlock) void k_batch_color(int64_t G, gc_graph_desc* d,
+                                                            const int32_t* rowptr_base,
+                                                            const int32_t* colidx_base,
+                                                            int32_t* colors_base, int max_rounds,
+                                                            const int32_t* order,
+                                                            BatchCtrl* ctrl) {
+  extern __shared__ char smem[];
+  __shared__ int sh_idx, sh_max;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      sh_idx = atomicAdd(&ctrl->queue, 1);
+      sh_max = 0;
+    }
+    __syncthreads();
+    const int idx = sh_idx;
+    if (idx >= G) break;  // workgroup-uniform
+    const int gi = order[idx];
+    const gc_graph_desc x = d[gi];
+    GraphRun g;
+    g.rp = rowptr_base + x.rowptr_off;
+    g.ci = colidx_base + x.colidx_off;
+    g.out = colors_base + x.color_off;
+    g.n = x.n;
+    g.rounds_in = x.rounds;
+    g.max_rounds = max_rounds;
+    int mx = 0;
+    for (int v = threadIdx.x; v < g.n; v += blockDim.x) mx = max(mx, g.rp[v + 1] - g.rp[v]);
+    if (mx) atomicMax(&sh_max, mx);
+    __syncthreads();
+    const int maxdeg = sh_max;
+    const int64_t nnz = g.n > 0 ? (int64_t)g.rp[g.n] : 0;
+    const double avg = g.n > 0 ? (double)nnz / g.n : 0.0;
+    int left = 0, rounds;
+    if (avg >= 32.0) rounds = dispatch_state<16>(g, maxdeg, smem, &left);
+    else if (avg >= 16.0) rounds = dispatch_state<8>(g, maxdeg, smem, &left);
+    else if (avg >= 8.0) rounds = dispatch_state<4>(g, maxdeg, smem, &left);
+    else rounds = dispatch_state<2>(g, maxdeg, smem, &left);
+    if (threadIdx.x == 0) {
+      d[gi].rounds = rounds;
+      d[gi].active = left;
+      d[gi].max_degree = maxdeg;
+    }
+    __syncthreads();  // sh_idx / sh_max are rewritten for the next graph
+  }
+}
+
+__global__ void k_batch_rounds_out(int64_t G, const gc_graph_desc* d, int32_t* rounds_out) {
+  const long tid = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const long nth = (long)gridDim.x * blockDim.x;
+  for (long g = tid; g < G; g += nth) rounds_out[g] = d[g].rounds;
+}
+
+static int batch_grid(int64_t G) {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 1;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 1;
+  const int64_t per_cu = 2;  // two 64 KB LDS slices per 160 KB compute unit
+  return (int)(G < per_cu * cus ? G : per_cu * cus);
+}
+
+static int run_batch(int64_t G, gc_graph_desc* d, const int32_t* rpb, const int32_t* cib,
+                     int32_t* colb, int max_rounds, void* ws, hipStream_t s) {
+  static bool lds_set = false;
+  if (!lds_set) {  // allow the 64 KB dynamic slice on top of the static LDS
+    hipError_t e = hipFuncSetAttribute((const void*)k_batch_color,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, kBatchLds);
+    if (e != hipSuccess) return (int)e;
+    lds_set = true;
+  }
+  BatchCtrl* ctrl = (BatchCtrl*)ws;
+  int32_t* order = (int32_t*)((char*)ws + ws_order_off());
+  hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(1024), 0, s, G, d, rpb, order, ctrl);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return (int)e;
+  hipLaunchKernelGGL(k_batch_color, dim3(batch_grid(G)), dim3(kBatchBlock), kBatchLds, s, G, d, rpb,
+                     cib, colb, max_rounds, order, ctrl);
+  return (int)hipGetLastError();
+}
+
+}  // namespace gc
+
+using namespace gc;
+
+namespace {
+int fail(int code, const char* msg) {
+  set_thread_error(msg);
+  return code;
+}
+}  // namespace
+
+extern "C" size_t gc_batch_workspace_bytes(int64_t num_graphs, const int64_t* voff,
+                                           const int64_t* eoff) {
+  if (num_graphs < 0 || num_graphs > INT32_MAX || !voff || !eoff) return 0;
+  if (voff[0] != 0 || eoff[0] != 0) return 0;
+  for (int64_t g = 0; g < num_graphs; ++g) {
+    const int64_t n = voff[g + 1] - voff[g], nnz = eoff[g + 1] - eoff[g];
+    if (n < 0 || nnz < 0 || n >= INT32_MAX || nnz > INT32_MAX) return 0;
+  }
+  return ws_descs_off(num_graphs) + (size_t)num_graphs * sizeof(gc_graph_desc) + 256;
+}
+
+extern "C" int gc_color_batch(int64_t num_graphs, const int64_t* voff, const int64_t* eoff,
+                              const int32_t* rowptr_local, const int32_t* colidx_local,
+                              int32_t* colors_out, int32_t* rounds_out, void* workspace,
+                              size_t workspace_bytes, void* stream) {
+  if (num_graphs < 0 || num_graphs > INT32_MAX) return fail(GC_EINVAL, "gc_color_batch: bad num_graphs");
+  if (num_graphs == 0) return GC_OK;
+  if (!voff || !eoff || !rowptr_local || !workspace)
+    return fail(GC_EINVAL, "gc_color_batch: NULL array");
+  const size_t need = ws_descs_off(num_graphs) + (size_t)num_graphs * sizeof(gc_graph_desc) + 256;
+  if (workspace_bytes < need) return fail(GC_EINVAL, "gc_color_batch: workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  (void)hipGetLastError();
+  gc_graph_desc* d = (gc_graph_desc*)((char*)workspace + ws_descs_off(num_graphs));
+  const int grid = (int)((num_graphs + 255) / 256 < 4096 ? (num_graphs + 255) / 256 : 4096);
+  hipLaunchKernelGGL(k_batch_descs, dim3(grid), dim3(256), 0, s, num_graphs, voff, eoff, d);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(GC_EDEVICE, hipGetErrorString(e));
+  int rc = run_batch(num_graphs, d, rowptr_local, colidx_local, colors_out, 0, workspace, s);
+  if (rc) return fail(GC_EDEVICE, hipGetErrorString((hipError_t)rc));
+  if (rounds_out) {
+    hipLaunchKernelGGL(k_batch_rounds_out, dim3(grid), dim3(256), 0, s, num_graphs, d, rounds_out);
+    e = hipGetLastError();
+    if (e != hipSuccess) return fail(GC_EDEVICE, hipGetErrorString(e));
+  }
+  return GC_OK;
+}
+
+extern "C" size_t gc_batch_step_workspace_bytes(int64_t num_graphs, int64_t total_vertices) {
+  if (num_graphs < 0 || num_graphs > INT32_MAX || total_vertices < 0) return 0;
+  return ws_order_off() + (size_t)num_graphs * sizeof(int32_t) + 256;
+}
+
+extern "C" int gc_batch_step(int64_t num_graphs, gc_graph_desc* descs, const int32_t* rowptr_base,
+                             const int32_t* colidx_base, int32_t* colors_base, int32_t max_rounds,
+                             void* workspace, size_t workspace_bytes, void* stream) {
+  if (num_graphs < 0 || num_graphs > INT32_MAX) return fail(GC_EINVAL, "gc_batch_step: bad num_graphs");
+  if (num_graphs == 0) return GC_OK;
+  if (!descs || !rowptr_base || !workspace) return fail(GC_EINVAL, "gc_batch_step: NULL array");
+  if (max_rounds < 0) return fail(GC_EINVAL, "gc_batch_step: negative max_rounds");
+  if (workspace_bytes < gc_batch_step_workspace_bytes(num_graphs, 0))
+    return fail(GC_EINVAL, "gc_batch_step: workspace too small");
+  (void)hipGetLastError();
+  int rc = run_batch(num_graphs, descs, rowptr_base, colidx_base, colors_base, max_rounds,
+                     workspace, (hipStream_t)stream);
+  if (rc) return fail(GC_EDEVICE, hipGetErrorString((hipError_t)rc));
+  return GC_OK;
 }

@@ -1,0 +1,118 @@
+// gc_device.h -- device helpers shared by the per-graph and batched kernels:
+// cross-lane reductions for wave64 and the per-vertex speculate / detect
+// work of a group of L lanes.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "gc_internal.h"
+
+namespace gc {
+
+// ------------------------------------------------------------ helpers --
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t x, int mask) {
+  int lo = __shfl_xor((int)(uint32_t)x, mask);
+  int hi = __shfl_xor((int)(uint32_t)(x >> 32), mask);
+  return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+template <typename T>
+__device__ __forceinline__ T shfl_any(T x, int src);
+template <>
+__device__ __forceinline__ int32_t shfl_any<int32_t>(int32_t x, int src) {
+  return __shfl(x, src);
+}
+template <>
+__device__ __forceinline__ int64_t shfl_any<int64_t>(int64_t x, int src) {
+  int lo = __shfl((int)(uint32_t)x, src);
+  int hi = __shfl((int)(uint32_t)((uint64_t)x >> 32), src);
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+template <int L>
+__device__ __forceinline__ uint64_t group_or(uint64_t m) {
+#pragma unroll
+  for (int off = L / 2; off > 0; off >>= 1) m |= shfl_xor64(m, off);
+  return m;
+}
+
+// position of the k-th (0-based) set bit of m; k < popcount(m)
+__device__ __forceinline__ int nth_set_bit(uint64_t m, int k) {
+  int pos = 0;
+#pragma unroll
+  for (int w = 32; w > 0; w >>= 1) {
+    int c = __popcll((m >> pos) & ((1ull << w) - 1));
+    if (k >= c) {
+      k -= c;
+      pos += w;
+    }
+  }
+  return pos;
+}
+
+// tentative colour carried by a state word (final colours decode to themselves)
+__device__ __forceinline__ int tent_of(int s) { return s < 0 ? ~s : s; }
+
+// ------------------------------------------- per-vertex work, L lanes --
+
+// Least colour not final on any neighbour of the row [b, e), computed by a
+// group of L lanes (gl = lane in group).  Every lane returns the result.
+template <typename RP, typename S, int L>
+__device__ __forceinline__ int spec_group(const int32_t* __restrict__ colidx,
+                                          const S* __restrict__ st, RP b, RP e,
+                                          int gl) {
+  int base = 0;
+  for (;;) {
+    uint64_t m = 0;
+    RP k = b + gl;
+    for (; k + L < e; k += 2 * L) {  // two gathers in flight per lane
+      int u0 = colidx[k];
+      int u1 = colidx[k + L];
+      int c0 = st[u0];
+      int c1 = st[u1];
+      unsigned r0 = (unsigned)c0 - (unsigned)base;
+      unsigned r1 = (unsigned)c1 - (unsigned)base;
+      if (c0 >= 0 && r0 < 64u) m |= 1ull << r0;
+      if (c1 >= 0 && r1 < 64u) m |= 1ull << r1;
+    }
+    if (k < e) {
+      int c0 = st[colidx[k]];
+      unsigned r0 = (unsigned)c0 - (unsigned)base;
+      if (c0 >= 0 && r0 < 64u) m |= 1ull << r0;
+    }
+    m = group_or<L>(m);
+    if (m != ~0ull) return base + __builtin_ctzll(~m);
+    base += 64;  // all of base..base+63 are taken: slide the window
+  }
+}
+
+// Does a lower-id neighbour of v carry tentative colour t?  Group of L lanes.
+// With sorted rows the scan stops at the first neighbour id >= v.
+template <typename RP, typename S, int L>
+__device__ __forceinline__ bool detect_group(const int32_t* __restrict__ colidx,
+                                             const S* __restrict__ st, RP b, RP e,
+                                             int v, int t, int gl, uint64_t gmask, bool sorted) {
+  for (RP kb = b; kb < e; kb += L) {
+    RP k = kb + gl;
+    bool conf = false, past = false;
+    if (k < e) {
+      int u = colidx[k];
+      if (u < v) {
+        conf = tent_of(st[u]) == t;
+      } else {
+        past = true;
+      }
+    } else {
+      past = true;
+    }
+    if (__ballot(conf) & gmask) return true;
+    if (sorted && (__ballot(past) & gmask)) return false;
+  }
+  return false;
+}
+
+}  // namespace gc

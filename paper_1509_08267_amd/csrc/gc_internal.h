@@ -58,6 +58,9 @@ struct KArgs {
   Ctrl* ctrl;
 };
 
+// Records `msg` as the calling thread's last error (gc_last_error(NULL)).
+void set_thread_error(const char* msg);
+
 // Launch helpers implemented in gc_kernels.hip.  All return a hipError_t
 // cast to int.  `sbytes` is the state width in bytes (1, 2 or 4).
 int launch_init(const KArgs& a, void* stream);

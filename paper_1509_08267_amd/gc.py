@@ -283,3 +283,58 @@ def color(rowptr: torch.Tensor, colidx: torch.Tensor, **kw) -> torch.Tensor:
         out = g.color()
         g.stats()
         return out
+
+
+def color_batch(voff, eoff, rowptr_local, colidx_local, *, voff_host=None, eoff_host=None,
+                stream=None):
+    """Colour every graph of a packed batch in one launch (gc_color_batch).
+
+    voff/eoff/rowptr_local/colidx_local are device tensors (int64, int64,
+    int32, int32); voff_host/eoff_host (numpy) size the workspace and are
+    copied from the device when not given.  Returns (colors, rounds) device
+    tensors; the work is queued on `stream` (not synchronised)."""
+    import numpy as np
+    G = int(voff.numel()) - 1
+    vh = np.asarray(voff_host if voff_host is not None else voff.cpu().numpy(), dtype=np.int64)
+    eh = np.asarray(eoff_host if eoff_host is not None else eoff.cpu().numpy(), dtype=np.int64)
+    nbytes = gc_batch_workspace_bytes(G, vh, eh)
+    if nbytes == 0 and G > 0:
+        raise GCError(GC_EINVAL, "gc_batch_workspace_bytes rejected the offsets")
+    dev = colidx_local.device if colidx_local.numel() else rowptr_local.device
+    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+    colors = torch.empty(max(int(vh[-1]), 1), dtype=torch.int32, device=dev)
+    rounds = torch.empty(max(G, 1), dtype=torch.int32, device=dev)
+    gc_color_batch(G, voff, eoff, rowptr_local, colidx_local, colors, rounds, ws, nbytes, stream)
+    return colors[: int(vh[-1])], rounds[:G]
+
+
+DESC_DTYPE = None
+
+
+def desc_array(rows):
+    """numpy structured array of gc_graph_desc from (rowptr_off, colidx_off,
+    color_off, n, rounds) tuples."""
+    import numpy as np
+    global DESC_DTYPE
+    if DESC_DTYPE is None:
+        DESC_DTYPE = np.dtype([("rowptr_off", "<i8"), ("colidx_off", "<i8"), ("color_off", "<i8"),
+                               ("n", "<i4"), ("rounds", "<i4"), ("active", "<i4"),
+                               ("max_degree", "<i4")])
+        assert DESC_DTYPE.itemsize == ctypes.sizeof(gc_graph_desc)
+    a = np.zeros(len(rows), DESC_DTYPE)
+    for i, r in enumerate(rows):
+        a[i] = (r[0], r[1], r[2], r[3], r[4] if len(r) > 4 else 0, 0, 0)
+    return a
+
+
+def batch_step(descs_dev, rowptr_base, colidx_base, colors_base, max_rounds, *, workspace=None,
+               stream=None):
+    """Advance the graphs described by `descs_dev` (a uint8 device tensor
+    holding gc_graph_desc records) by at most max_rounds rounds."""
+    G = int(descs_dev.numel()) // ctypes.sizeof(gc_graph_desc)
+    need = gc_batch_step_workspace_bytes(G, 0)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=descs_dev.device)
+    gc_batch_step(G, descs_dev, rowptr_base, colidx_base, colors_base, max_rounds, workspace,
+                  int(workspace.numel()), stream)
+    return workspace
