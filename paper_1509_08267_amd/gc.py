@@ -321,10 +321,8 @@ def desc_array(rows):
                                ("n", "<i4"), ("rounds", "<i4"), ("active", "<i4"),
                                ("max_degree", "<i4")])
         assert DESC_DTYPE.itemsize == ctypes.sizeof(gc_graph_desc)
-    a = np.zeros(len(rows), DESC_DTYPE)
-    for i, r in enumerate(rows):
-        a[i] = (r[0], r[1], r[2], r[3], r[4] if len(r) > 4 else 0, 0, 0)
-    return a
+    return np.array([(r[0], r[1], r[2], r[3], r[4] if len(r) > 4 else 0, 0, 0) for r in rows],
+                    dtype=DESC_DTYPE)
 
 
 def batch_step(descs_dev, rowptr_base, colidx_base, colors_base, max_rounds, *, workspace=None,
