@@ -149,11 +149,25 @@ enum gc_option {
                                 1..6 (4); more are not reliably co-resident   */
   GC_OPT_STATE_BYTES = 12,   /* (get only) bytes per vertex of the working state:
                                 1 if max degree <= 127, 2 if <= 32767, else 4 */
-  GC_OPT_PROFILE = 13        /* 1: time the kernels of each call with HIP events
+  GC_OPT_PROFILE = 13,       /* 1: time the kernels of each call with HIP events
                                 recorded on the call's stream; once R is known
                                 the rounds are launched directly (not as a
                                 captured graph) with an event around every
                                 kernel; read with gc_get_profile           */
+  GC_OPT_ALGORITHM = 14      /* enum gc_algorithm (default GC_ALGO_AUTO)           */
+};
+/* How speculation learns the final colours of a vertex's neighbours.  Both
+ * give the same colouring. */
+enum gc_algorithm {
+  GC_ALGO_AUTO = 0,  /* currently PUSH                                             */
+  GC_ALGO_PULL = 1,  /* each round, each uncoloured vertex gathers the state of all
+                        its neighbours and builds its forbidden-colour mask        */
+  GC_ALGO_PUSH = 2   /* a vertex whose colour c < 32 becomes final marks colour c
+                        as taken in a 32-byte flag block of each neighbour (one
+                        plain byte store per CSR entry over the whole colouring,
+                        no atomics); speculation reads its 32 flags and scans its
+                        row only when colours 0..31 are all taken.  32 bytes per
+                        vertex of device memory                                 */
 };
 enum gc_mode {
   GC_MODE_AUTO = 0,       /* currently GRAPH                                      */

@@ -49,7 +49,7 @@ struct Pinned {  // read-back area in pinned host memory
 struct Captured {  // one instantiated chunk of K rounds
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  int k = 0, lanes = 0, light = 0;
+  int k = 0, lanes = 0, light = 0, push = 0;
 };
 
 // Kernel kinds reported by gc_get_profile.
@@ -72,6 +72,8 @@ struct gc_ctx {
   int32_t* mlist = nullptr;   // device, n
   int32_t* hlist = nullptr;   // device, n
   int32_t* dcounts = nullptr; // device, 8 ints: classify counts, validate err
+  uint8_t* seen = nullptr;    // device, n * kPushColors (push algorithm), allocated on first use
+  int epoch = 0;              // epoch of the last call's pushed flags (1..255)
   Pinned* host = nullptr;     // pinned
   int32_t mcount = 0, hcount = 0, maxdeg = 0;
 
@@ -84,6 +86,7 @@ struct gc_ctx {
   int persist_per_cu = 4; // co-resident workgroups per CU of the persistent kernel
   int max_rounds = 0;
   int chunk_rounds = 16;
+  int algorithm = GC_ALGO_AUTO;
   bool lists_dirty = false;
 
   // last colouring
@@ -138,7 +141,7 @@ static int auto_lanes(const gc_ctx* h) {
   if (h->lanes) return h->lanes;
   double avg = h->n ? (double)h->m / (double)h->n : 0.0;
   int L = 2;
-  while (L < 32 && L * 2 <= avg) L *= 2;  // about two entries per lane
+  while (L < 32 && L * 4 <= avg) L *= 2;  // about four row entries per lane
   return L;
 }
 
@@ -151,6 +154,10 @@ static int state_bytes(int32_t maxdeg) {
   if (maxdeg <= 127) return 1;
   if (maxdeg <= 32767) return 2;
   return 4;
+}
+
+static bool use_push(const gc_ctx* h) {
+  return h->algorithm == GC_ALGO_PUSH || h->algorithm == GC_ALGO_AUTO;
 }
 
 static KArgs make_args(const gc_ctx* h, int32_t* colors, int light_max) {
@@ -166,6 +173,10 @@ static KArgs make_args(const gc_ctx* h, int32_t* colors, int light_max) {
   a.hlist = h->hlist;
   a.hcount = h->hcount;
   a.sorted = (h->flags & GC_ROWS_SORTED) != 0;
+  a.push = use_push(h) ? 1 : 0;
+  a.seen = h->seen;
+  a.epoch = h->epoch;
+  a.clear_seen = h->epoch == 1;
   a.ctrl = h->ctrl;
   return a;
 }
@@ -210,6 +221,7 @@ static void free_ctx(gc_ctx* h) {
   if (h->mlist) (void)hipFree(h->mlist);
   if (h->hlist) (void)hipFree(h->hlist);
   if (h->dcounts) (void)hipFree(h->dcounts);
+  if (h->seen) (void)hipFree(h->seen);
   if (h->host) (void)hipHostFree(h->host);
   delete h;
 }
@@ -348,11 +360,12 @@ static int capture(gc_ctx* h, Captured& c, const KArgs& a, int L, int K) {
   c.k = K;
   c.lanes = L;
   c.light = a.light_max;
+  c.push = a.push;
   return GC_OK;
 }
 
-static bool usable(const Captured& c, int K, int L, int light) {
-  return c.exec && c.k == K && c.lanes == L && c.light == light;
+static bool usable(const Captured& c, int K, int L, int light, int push) {
+  return c.exec && c.k == K && c.lanes == L && c.light == light && c.push == push;
 }
 
 static float elapsed(hipEvent_t a, hipEvent_t b) {
@@ -424,6 +437,16 @@ extern "C" int gc_color(gc_handle h, int32_t* colors_out, void* stream) {
     if (rc) return rc;
   }
   (void)hipGetLastError();  // launch checks below must see only this call's errors
+  if (use_push(h)) {
+    if (!h->seen && h->n > 0) {
+      hipError_t e = hipMalloc((void**)&h->seen, (size_t)h->n * gc::kPushColors);
+      if (e != hipSuccess) return set_err(h, GC_ENOMEM, "colour flags: %s", hipGetErrorString(e));
+      h->epoch = 0;
+    }
+    // a new epoch per call marks this call's flags; flags are cleared on the
+    // first call and whenever the 8-bit epoch wraps
+    h->epoch = h->epoch % 255 + 1;
+  }
   h->stats_ready = false;
   const int L = auto_lanes(h);
   const int light = light_max_of(h, L);
@@ -464,7 +487,7 @@ extern "C" int gc_color(gc_handle h, int32_t* colors_out, void* stream) {
       // R is known: queue rounds 2..R in one captured chunk, no read-back.
       const int K = (int)h->known_rounds - 1;
       if (K > 0) {
-        if (!usable(h->exact, K, L, light)) {
+        if (!usable(h->exact, K, L, light, a.push)) {
           rc = capture(h, h->exact, a, L, K);
           if (rc) return rc;
         }
@@ -491,7 +514,7 @@ extern "C" int gc_color(gc_handle h, int32_t* colors_out, void* stream) {
           }
           r = upto;
         } else if (mode == GC_MODE_GRAPH) {
-          if (!usable(h->chunk, K, L, light)) {
+          if (!usable(h->chunk, K, L, light, a.push)) {
             rc = capture(h, h->chunk, a, L, K);
             if (rc) return rc;
           }
@@ -606,6 +629,10 @@ extern "C" int gc_set_option(gc_handle h, int option, int64_t value) {
       if (value < 1 || value > 6) break;
       h->persist_per_cu = (int)value;
       return GC_OK;
+    case GC_OPT_ALGORITHM:
+      if (value < GC_ALGO_AUTO || value > GC_ALGO_PUSH) break;
+      h->algorithm = (int)value;
+      return GC_OK;
     case GC_OPT_PROFILE:
       if (value < 0 || value > 1) break;
       if (value && !h->pev[0]) {
@@ -636,6 +663,7 @@ extern "C" int gc_get_option(gc_handle h, int option, int64_t* value) {
     case GC_OPT_PERSISTENT_BLOCKS_PER_CU: *value = h->persist_per_cu; return GC_OK;
     case GC_OPT_STATE_BYTES: *value = h->sbytes; return GC_OK;
     case GC_OPT_PROFILE: *value = h->profile; return GC_OK;
+    case GC_OPT_ALGORITHM: *value = use_push(h) ? GC_ALGO_PUSH : GC_ALGO_PULL; return GC_OK;
     default: return set_err(h, GC_EINVAL, "gc_get_option: unknown option %d", option);
   }
 }

@@ -64,8 +64,8 @@ __device__ __forceinline__ int tent_of(int s) { return s < 0 ? ~s : s; }
 template <typename RP, typename S, int L>
 __device__ __forceinline__ int spec_group(const int32_t* __restrict__ colidx,
                                           const S* __restrict__ st, RP b, RP e,
-                                          int gl) {
-  int base = 0;
+                                          int gl, int base0 = 0) {
+  int base = base0;
   for (;;) {
     uint64_t m = 0;
     RP k = b + gl;
@@ -88,6 +88,31 @@ __device__ __forceinline__ int spec_group(const int32_t* __restrict__ colidx,
     if (m != ~0ull) return base + __builtin_ctzll(~m);
     base += 64;  // all of base..base+63 are taken: slide the window
   }
+}
+
+// A vertex that has just committed colour t < kPushColors marks colour t as
+// taken for all its neighbours (row [b, e)): byte t of each neighbour's flag
+// block gets the call's epoch.  Plain byte stores: concurrent writers touch
+// different bytes or write the same value.  A group of `step` lanes.
+template <typename RP>
+__device__ __forceinline__ void push_colour(const int32_t* __restrict__ colidx, uint8_t* seen,
+                                            RP b, RP e, int t, int epoch, int gl, int step) {
+  for (RP k = b + gl; k < e; k += step) seen[(size_t)colidx[k] * kPushColors + t] = (uint8_t)epoch;
+}
+
+// Bit c of the result is set when byte c of v's flag block equals epoch
+// (a neighbour of v has final colour c), for c < kPushColors = 32.
+__device__ __forceinline__ uint32_t taken_colours(const uint8_t* seen, int v, int epoch) {
+  const uint4* p = (const uint4*)(seen + (size_t)v * kPushColors);
+  const uint4 x = p[0], y = p[1];
+  const uint32_t w[8] = {x.x, x.y, x.z, x.w, y.x, y.y, y.z, y.w};
+  uint32_t m = 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      m |= (uint32_t)(((w[i] >> (8 * j)) & 0xffu) == (uint32_t)epoch) << (4 * i + j);
+  return m;
 }
 
 // Does a lower-id neighbour of v carry tentative colour t?  Group of L lanes.

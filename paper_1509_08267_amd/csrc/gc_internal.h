@@ -23,6 +23,7 @@ constexpr int kBlock = 256;         // threads per workgroup of the round kernel
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kTraceRounds = 65536; // rounds whose |U_r| is recorded
 constexpr int kHeavyWindow = 4096;  // LDS colour window of the block-per-vertex path (bits)
+constexpr int kPushColors = 32;     // colours tracked per vertex by pushed flags
 
 // One 128-byte line per field that different blocks write, so that flags and
 // counters never share a line.
@@ -39,6 +40,7 @@ struct Ctrl {
   Line bar;              // grid barrier arrivals (monotonic within a launch)
   Line abort;            // set when a barrier wait exceeded its spin limit
   Line left;             // vertices still uncoloured after the last round
+  Line epoch;            // value marking this call's pushed colour flags (1..255)
   int32_t trace[kTraceRounds];  // |U_r| at slot r - 1
 };
 
@@ -55,6 +57,11 @@ struct KArgs {
   const int32_t* hlist;   // heavy vertices: a whole workgroup each
   int32_t hcount;
   int32_t sorted;         // rows ascending: the conflict scan may stop early
+  int32_t push;           // forbidden colours pushed by committing neighbours
+  uint8_t* seen;          // n * kPushColors: byte c of v == epoch when a neighbour of v
+                          // has final colour c (plain byte stores, no atomics)
+  int32_t epoch;          // epoch of this call (written to ctrl by the init kernel)
+  int32_t clear_seen;     // the init kernel zeroes `seen` (first call, epoch wrap)
   Ctrl* ctrl;
 };
 

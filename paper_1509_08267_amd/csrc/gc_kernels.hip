@@ -51,9 +51,9 @@ struct HeavySmem {
 
 template <typename RP, typename S>
 __device__ int spec_block(const int32_t* __restrict__ colidx, const S* __restrict__ st,
-                          RP b, RP e, HeavySmem& sm) {
+                          RP b, RP e, HeavySmem& sm, int base0 = 0) {
   const int tid = threadIdx.x;
-  int base = 0;
+  int base = base0;
   for (;;) {
     for (int w = tid; w < kHeavyWindow / 32; w += kBlock) sm.bm[w] = 0;
     if (tid == 0) sm.first = INT_MAX;
@@ -138,6 +138,8 @@ __device__ void light_phase(const KArgs& a, long wave_gid, long nwaves, Tally& t
   const RP* __restrict__ rp = (const RP*)a.rowptr;
   S* __restrict__ st = (S*)a.st;
   const bool sorted = a.sorted != 0;
+  const bool push = a.push != 0;
+  const int epoch = push ? a.ctrl->epoch.v : 0;
   const long nchunks = ((long)a.n + kWave - 1) / kWave;
   for (long ch = wave_gid; ch < nchunks; ch += nwaves) {
     const int v = (int)(ch * kWave) + lane;
@@ -146,6 +148,16 @@ __device__ void light_phase(const KArgs& a, long wave_gid, long nwaves, Tally& t
     RP b = 0, e = 0;
     if (v < a.n) {
       s = st[v];
+      if (PHASE == kSpec && push && s < 0) {
+        // pushed flags: the least colour absent from the final neighbours is
+        // the first colour not flagged, unless all of 0..31 are taken; those
+        // vertices (light ones here) scan their row from colour 32
+        const uint32_t m = taken_colours(a.seen, v, epoch);
+        if (m != ~0u) {
+          st[v] = (S)~__builtin_ctz(~m);
+          s = 0;
+        }
+      }
       if (s < 0) {
         b = rp[v];
         e = rp[v + 1];
@@ -165,7 +177,7 @@ __device__ void light_phase(const KArgs& a, long wave_gid, long nwaves, Tally& t
       const int vv = (int)(ch * kWave) + pos;
       if (valid) {  // group-uniform
         if (PHASE == kSpec) {
-          int t = spec_group<RP, S, L>(a.colidx, st, vb, ve, gl);
+          int t = spec_group<RP, S, L>(a.colidx, st, vb, ve, gl, push ? kPushColors : 0);
           if (gl == 0) st[vv] = (S)~t;
         } else {
           const int t = ~vs;
@@ -174,6 +186,7 @@ __device__ void light_phase(const KArgs& a, long wave_gid, long nwaves, Tally& t
             if (!lose) st[vv] = (S)t;
             tl.lost += lose;
           }
+          if (push && !lose && t < kPushColors) push_colour<RP>(a.colidx, a.seen, vb, ve, t, epoch, gl, L);
         }
         if (gl == 0) tl.active += 1;
       }
@@ -190,9 +203,13 @@ __device__ void medium_phase(const KArgs& a, long wave_gid, long nwaves, Tally& 
     const int v = a.mlist[i];
     const int s = st[v];
     if (s >= 0) continue;  // wave-uniform
+    // with pushed flags only the vertices whose colours 0..31 are all taken
+    // scan their row here (from colour 32); the others took their colour in
+    // the light pass
+    if (PHASE == kSpec && a.push && taken_colours(a.seen, v, a.ctrl->epoch.v) != ~0u) continue;
     const RP b = rp[v], e = rp[v + 1];
     if (PHASE == kSpec) {
-      int t = spec_group<RP, S, kWave>(a.colidx, st, b, e, lane);
+      int t = spec_group<RP, S, kWave>(a.colidx, st, b, e, lane, a.push ? kPushColors : 0);
       if (lane == 0) st[v] = (S)~t;
     } else {
       const int t = ~s;
@@ -201,6 +218,8 @@ __device__ void medium_phase(const KArgs& a, long wave_gid, long nwaves, Tally& 
         if (!lose) st[v] = (S)t;
         tl.lost += lose;
       }
+      if (a.push && !lose && t < kPushColors)
+        push_colour<RP>(a.colidx, a.seen, b, e, t, a.ctrl->epoch.v, lane, kWave);
     }
     if (lane == 0) tl.active += 1;
   }
@@ -213,11 +232,13 @@ __device__ void heavy_phase(const KArgs& a, long blk, long nblk, Tally& tl, Heav
   for (long i = blk; i < a.hcount; i += nblk) {
     const int v = a.hlist[i];
     const int s = st[v];
+    const bool skip =
+        PHASE == kSpec && a.push && taken_colours(a.seen, v, a.ctrl->epoch.v) != ~0u;
     __syncthreads();  // the commit below happens after every thread read s
-    if (s >= 0) continue;  // block-uniform
+    if (s >= 0 || skip) continue;  // block-uniform
     const RP b = rp[v], e = rp[v + 1];
     if (PHASE == kSpec) {
-      int t = spec_block<RP, S>(a.colidx, st, b, e, sm);
+      int t = spec_block<RP, S>(a.colidx, st, b, e, sm, a.push ? kPushColors : 0);
       if (threadIdx.x == 0) st[v] = (S)~t;
     } else {
       const int t = ~s;
@@ -226,6 +247,8 @@ __device__ void heavy_phase(const KArgs& a, long blk, long nblk, Tally& tl, Heav
         if (!lose) st[v] = (S)t;
         tl.lost += lose;
       }
+      if (a.push && !lose && t < kPushColors)
+        push_colour<RP>(a.colidx, a.seen, b, e, t, a.ctrl->epoch.v, threadIdx.x, kBlock);
     }
     if (threadIdx.x == 0) tl.active += 1;
   }
@@ -317,6 +340,10 @@ __global__ void k_init(KArgs a) {
   const long tid = blockIdx.x * (long)blockDim.x + threadIdx.x;
   const long nth = (long)gridDim.x * blockDim.x;
   for (long i = tid; i < kTraceRounds; i += nth) a.ctrl->trace[i] = 0;
+  if (a.push && a.clear_seen) {
+    uint4* p = (uint4*)a.seen;  // kPushColors bytes per vertex = 2 x 16 bytes
+    for (long i = tid; i < 2l * a.n; i += nth) p[i] = make_uint4(0, 0, 0, 0);
+  }
   if (tid == 0) {
     a.ctrl->more[0].v = 0;
     a.ctrl->more[1].v = a.n > 0;  // round 1 has work iff there are vertices
@@ -327,6 +354,7 @@ __global__ void k_init(KArgs a) {
     a.ctrl->bar.v = 0;
     a.ctrl->abort.v = 0;
     a.ctrl->left.v = 0;
+    a.ctrl->epoch.v = a.epoch;
   }
 }
 
@@ -523,7 +551,7 @@ static int launch_round_t(const KArgs& a, int phase_id, int round, bool from_bas
 
 template <typename RP, typename S, int L>
 static int launch_round1_t(const KArgs& a, int grid, hipStream_t s) {
-  if (a.sorted) {
+  if (a.sorted && !a.push) {
     hipLaunchKernelGGL((k_round1_sorted<RP, S>), dim3(grid), dim3(kBlock), 0, s, a);
     return (int)hipGetLastError();
   }
@@ -601,7 +629,8 @@ int persistent_max_grid(bool rp64, int sbytes, int lanes, int* grid_out) {
 }
 
 int launch_init(const KArgs& a, void* stream) {
-  hipLaunchKernelGGL(k_init, dim3(64), dim3(kBlock), 0, (hipStream_t)stream, a);
+  hipLaunchKernelGGL(k_init, dim3(a.push && a.clear_seen ? 1024 : 64), dim3(kBlock), 0,
+                     (hipStream_t)stream, a);
   return (int)hipGetLastError();
 }
 

@@ -28,7 +28,9 @@ GC_ROWPTR_I64, GC_VALIDATE, GC_ROWS_SORTED = 1, 2, 4
 (GC_OPT_MODE, GC_OPT_LANES, GC_OPT_HEAVY_DEGREE, GC_OPT_BLOCKS_PER_CU, GC_OPT_MAX_ROUNDS,
  GC_OPT_CHUNK_ROUNDS, GC_OPT_MEDIUM_DEGREE, GC_OPT_MAX_DEGREE, GC_OPT_MEDIUM_COUNT,
  GC_OPT_HEAVY_COUNT, GC_OPT_PERSISTENT_BLOCKS_PER_CU, GC_OPT_STATE_BYTES,
- GC_OPT_PROFILE) = range(1, 14)
+ GC_OPT_PROFILE, GC_OPT_ALGORITHM) = range(1, 15)
+GC_ALGO_AUTO, GC_ALGO_PULL, GC_ALGO_PUSH = range(3)
+ALGORITHMS = {"auto": GC_ALGO_AUTO, "pull": GC_ALGO_PULL, "push": GC_ALGO_PUSH}
 PROFILE_KINDS = ("round1", "speculate", "detect", "finish")
 # enum gc_mode
 GC_MODE_AUTO, GC_MODE_HOST, GC_MODE_CHUNKED, GC_MODE_PERSISTENT, GC_MODE_GRAPH = range(5)
@@ -230,11 +232,13 @@ class Graph:
              "blocks_per_cu": GC_OPT_BLOCKS_PER_CU, "max_rounds": GC_OPT_MAX_ROUNDS,
              "chunk_rounds": GC_OPT_CHUNK_ROUNDS, "medium_degree": GC_OPT_MEDIUM_DEGREE,
              "persistent_blocks_per_cu": GC_OPT_PERSISTENT_BLOCKS_PER_CU,
-             "profile": GC_OPT_PROFILE}
+             "profile": GC_OPT_PROFILE, "algorithm": GC_OPT_ALGORITHM}
 
     def set(self, name: str, value):
         if name == "mode" and isinstance(value, str):
             value = MODES[value]
+        if name == "algorithm" and isinstance(value, str):
+            value = ALGORITHMS[value]
         gc_set_option(self.h, self._OPTS[name], value)
 
     def get(self, option: int) -> int:

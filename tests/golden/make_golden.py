@@ -41,6 +41,18 @@ def one(name):
         t = time.perf_counter()
         colors, rounds = oracle.rsc_batch(inp.voff, inp.eoff, inp.rowptr_local, inp.colidx_local)
         rec["oracle_seconds"] = time.perf_counter() - t
+        # per-round totals over all graphs (for algorithmic byte counts)
+        sa = sd = sl = 0
+        for g in range(inp.num_graphs):
+            sub = inp.graph(g)
+            r = oracle.rsc(sub.rowptr, sub.colidx)
+            assert np.array_equal(r.colors, colors[inp.voff[g]:inp.voff[g + 1]])
+            sa += int(r.trace[:, 0].sum())
+            sd += int(r.trace[:, 1].sum())
+            sl += int(r.trace[:, 2].sum())
+        rec["sum_active"] = sa
+        rec["sum_active_deg"] = sd
+        rec["sum_active_lower_deg"] = sl
         rec["colors_sha256"] = colors_sha(colors)
         rec["rounds_sha256"] = hashlib.sha256(rounds.astype(np.int64).tobytes()).hexdigest()
         rec["rounds_max"] = int(rounds.max())

@@ -19,6 +19,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 MODES = ["host", "chunked", "graph", "persistent"]
+ALGOS = ["pull", "push"]
 GOLDEN = json.load(open(os.path.join(ROOT, "tests", "golden", "workloads.json")))
 
 
@@ -69,11 +70,12 @@ def _named_cases():
     ]
 
 
+@pytest.mark.parametrize("algorithm", ALGOS)
 @pytest.mark.parametrize("mode", MODES)
-def test_named_graphs_every_mode(gc, mode):
+def test_named_graphs_every_mode(gc, mode, algorithm):
     for name, g in _named_cases():
-        print(f"[case] {name} mode={mode}", flush=True)
-        assert_parity(gc, g, mode=mode)
+        print(f"[case] {name} mode={mode} algorithm={algorithm}", flush=True)
+        assert_parity(gc, g, mode=mode, algorithm=algorithm)
 
 
 def test_no_vertices(gc):
@@ -88,8 +90,9 @@ def test_every_lane_width(gc, lanes):
     for seed, (n, m) in enumerate([(5000, 60000), (777, 20000)]):
         g = graphgen.er(n, m, 100 + seed)
         print(f"[case] er n={n} m={m} lanes={lanes}", flush=True)
-        assert_parity(gc, g, lanes=lanes, mode="persistent")
-        assert_parity(gc, g, lanes=lanes, mode="chunked")
+        for algo in ALGOS:
+            assert_parity(gc, g, lanes=lanes, mode="persistent", algorithm=algo)
+            assert_parity(gc, g, lanes=lanes, mode="chunked", algorithm=algo)
 
 
 def test_forced_medium_and_heavy_paths(gc):
@@ -99,18 +102,23 @@ def test_forced_medium_and_heavy_paths(gc):
     ref = oracle.rsc(g.rowptr, g.colidx)
     for medium, heavy in [(4, 30), (0, 1), (1, 2), (16, 40), (64, 100000)]:
         for mode in ("persistent", "host"):
-            print(f"[case] classes medium={medium} heavy={heavy} mode={mode}", flush=True)
-            assert_parity(gc, g, ref, mode=mode, medium_degree=medium or 1, heavy_degree=heavy)
+            for algo in ALGOS:
+                print(f"[case] classes medium={medium} heavy={heavy} mode={mode} {algo}", flush=True)
+                assert_parity(gc, g, ref, mode=mode, medium_degree=medium or 1, heavy_degree=heavy,
+                              algorithm=algo)
 
 
 def test_multiword_colour_windows(gc):
     # K_n needs colours up to n-1: beyond 64 (light/medium window) and with
     # heavy_degree small, beyond nothing; K_4200 would exceed the 4096-bit
     # heavy window but is large, so use a dense graph with heavy_degree low
+    # (with pushed masks, colours >= 64 take the row-scan fallback)
     g = graphgen.complete(300)
     for medium, heavy in [(0, 100000), (1, 100000), (1, 2)]:
-        print(f"[case] K300 medium={medium} heavy={heavy}", flush=True)
-        assert_parity(gc, g, mode="persistent", medium_degree=medium or 400, heavy_degree=heavy)
+        for algo in ALGOS:
+            print(f"[case] K300 medium={medium} heavy={heavy} {algo}", flush=True)
+            assert_parity(gc, g, mode="persistent", medium_degree=medium or 400, heavy_degree=heavy,
+                          algorithm=algo)
 
 
 def test_unsorted_rows_and_int64_rowptr(gc):
@@ -120,10 +128,12 @@ def test_unsorted_rows_and_int64_rowptr(gc):
         gs = graphgen.shuffle_rows(g, rng)
         for rp64 in (False, True):
             for sorted_rows, gg in ((True, g), (False, gs)):
-                print(f"[case] n={g.n} rp64={rp64} sorted={sorted_rows}", flush=True)
-                assert_parity(gc, gg, ref, rp64=rp64, rows_sorted=sorted_rows, mode="persistent")
-                assert_parity(gc, gg, ref, rp64=rp64, rows_sorted=sorted_rows, mode="host",
-                              medium_degree=8, heavy_degree=64)
+                for algo in ALGOS:
+                    print(f"[case] n={g.n} rp64={rp64} sorted={sorted_rows} {algo}", flush=True)
+                    assert_parity(gc, gg, ref, rp64=rp64, rows_sorted=sorted_rows,
+                                  mode="persistent", algorithm=algo)
+                    assert_parity(gc, gg, ref, rp64=rp64, rows_sorted=sorted_rows, mode="host",
+                                  medium_degree=8, heavy_degree=64, algorithm=algo)
 
 
 def test_random_small_graphs(gc):
@@ -132,7 +142,8 @@ def test_random_small_graphs(gc):
         n = int(rng.integers(1, 60))
         g = graphgen.random_small(n, float(rng.choice([0.05, 0.2, 0.6])), rng)
         mode = MODES[i % len(MODES)]
-        assert_parity(gc, g, mode=mode, lanes=int(rng.choice([2, 4, 16, 64])))
+        assert_parity(gc, g, mode=mode, lanes=int(rng.choice([2, 4, 16, 64])),
+                      algorithm=ALGOS[(i // len(MODES)) % 2])
 
 
 def test_validation_rejects_malformed_graphs(gc):
@@ -210,7 +221,8 @@ def test_state_widths(gc):
         with gc.Graph(rp, ci) as G:
             assert G.get(gc.GC_OPT_STATE_BYTES) == width
         for mode in ("graph", "host", "persistent"):
-            assert_parity(gc, g, mode=mode)
+            for algo in ALGOS:
+                assert_parity(gc, g, mode=mode, algorithm=algo)
 
 
 def test_changed_graph_is_reported(gc):
@@ -270,9 +282,10 @@ def test_long_path_many_rounds(gc):
         assert np.array_equal(col, np.arange(n, dtype=np.int32) % 2)
 
 
-def test_complete_2048(gc):
+@pytest.mark.parametrize("algorithm", ALGOS)
+def test_complete_2048(gc, algorithm):
     g = graphgen.complete(2048)
-    col, rounds, ncol, _ = gpu_color(gc, g, mode="persistent")
+    col, rounds, ncol, _ = gpu_color(gc, g, mode="persistent", algorithm=algorithm)
     assert rounds == 2048 and ncol == 2048
     assert np.array_equal(col, np.arange(2048, dtype=np.int32))
 
@@ -305,7 +318,8 @@ def test_workload_er_10k(gc):
 
 @pytest.mark.slow
 def test_workload_er_1m(gc):
-    g, col = _full(gc, "er_1m_16m")
+    _full(gc, "er_1m_16m", algorithm="pull")
+    g, col = _full(gc, "er_1m_16m", algorithm="push")
     ref = oracle.rsc(g.rowptr, g.colidx)   # the oracle itself, a few seconds
     assert np.array_equal(col, ref.colors)
     assert oracle.check_proper(g.rowptr, g.colidx, col) == 0
@@ -313,13 +327,15 @@ def test_workload_er_1m(gc):
 
 @pytest.mark.slow
 def test_workload_stencil(gc):
-    g, col = _full(gc, "stencil27_160")
+    _full(gc, "stencil27_160", algorithm="pull")
+    g, col = _full(gc, "stencil27_160", algorithm="push")
     assert oracle.check_proper(g.rowptr, g.colidx, col) == 0
     assert oracle.check_grundy(g.rowptr, g.colidx, col) == 0
 
 
 @pytest.mark.slow
 def test_workload_rmat(gc):
-    g, col = _full(gc, "rmat22_ef16")
+    _full(gc, "rmat22_ef16", algorithm="pull")
+    g, col = _full(gc, "rmat22_ef16", algorithm="push")
     assert oracle.check_proper(g.rowptr, g.colidx, col) == 0
     assert oracle.check_grundy(g.rowptr, g.colidx, col) == 0
