@@ -73,6 +73,9 @@ struct gc_ctx {
   int32_t* hlist = nullptr;   // device, n
   int32_t* dcounts = nullptr; // device, 8 ints: classify counts, validate err
   uint8_t* seen = nullptr;    // device, n * kPushColors (push algorithm), allocated on first use
+  uint8_t* wide = nullptr;    // device, wide_blocks * kWideColors (push algorithm)
+  int64_t wide_blocks = 0;    // blocks allocated in `wide`
+  int32_t* widx = nullptr;    // device, n: wide block of each medium/heavy vertex, -1 otherwise
   int epoch = 0;              // epoch of the last call's pushed flags (1..255)
   Pinned* host = nullptr;     // pinned
   int32_t mcount = 0, hcount = 0, maxdeg = 0;
@@ -177,6 +180,8 @@ static KArgs make_args(const gc_ctx* h, int32_t* colors, int light_max) {
   a.seen = h->seen;
   a.epoch = h->epoch;
   a.clear_seen = h->epoch == 1;
+  a.wide = h->wide;
+  a.widx = h->widx;
   a.ctrl = h->ctrl;
   return a;
 }
@@ -190,13 +195,14 @@ static int classify(gc_ctx* h, hipStream_t s) {
   const int heavy = std::max(h->heavy_min, light + 1);
   HIPCHECK(h, hipMemsetAsync(h->dcounts, 0, 3 * sizeof(int32_t), s));
   LCHECK(h, gc::launch_classify(h->rowptr, h->rp64, (int32_t)h->n, light, heavy, h->mlist, h->hlist,
-                                h->dcounts, grid_of(h), s));
+                                h->dcounts, h->widx, grid_of(h), s));
   HIPCHECK(h, hipMemcpyAsync(h->host->counts, h->dcounts, 3 * sizeof(int32_t),
                              hipMemcpyDeviceToHost, s));
   HIPCHECK(h, hipStreamSynchronize(s));
   h->mcount = h->host->counts[0];
   h->hcount = h->host->counts[1];
   h->maxdeg = h->host->counts[2];
+  LCHECK(h, gc::launch_wide_index(h->hlist, h->hcount, h->mcount, h->widx, s));
   h->lists_dirty = false;
   return GC_OK;
 }
@@ -222,6 +228,8 @@ static void free_ctx(gc_ctx* h) {
   if (h->hlist) (void)hipFree(h->hlist);
   if (h->dcounts) (void)hipFree(h->dcounts);
   if (h->seen) (void)hipFree(h->seen);
+  if (h->wide) (void)hipFree(h->wide);
+  if (h->widx) (void)hipFree(h->widx);
   if (h->host) (void)hipHostFree(h->host);
   delete h;
 }
@@ -267,6 +275,7 @@ extern "C" int gc_create(gc_handle* out, const void* rowptr, const int32_t* coli
   CREATE_CHECK(hipMalloc((void**)&h->mlist, (size_t)std::max<int64_t>(n, 1) * sizeof(int32_t)));
   CREATE_CHECK(hipMalloc((void**)&h->hlist, (size_t)std::max<int64_t>(n, 1) * sizeof(int32_t)));
   CREATE_CHECK(hipMalloc((void**)&h->dcounts, 8 * sizeof(int32_t)));
+  CREATE_CHECK(hipMalloc((void**)&h->widx, (size_t)std::max<int64_t>(n, 1) * sizeof(int32_t)));
   CREATE_CHECK(hipHostMalloc((void**)&h->host, sizeof(Pinned), hipHostMallocDefault));
   CREATE_CHECK(hipEventCreateWithFlags(&h->done, hipEventDisableTiming));
   memset(h->host, 0, sizeof(Pinned));
@@ -442,6 +451,18 @@ extern "C" int gc_color(gc_handle h, int32_t* colors_out, void* stream) {
       hipError_t e = hipMalloc((void**)&h->seen, (size_t)h->n * gc::kPushColors);
       if (e != hipSuccess) return set_err(h, GC_ENOMEM, "colour flags: %s", hipGetErrorString(e));
       h->epoch = 0;
+    }
+    const int64_t blocks = (int64_t)h->mcount + h->hcount;
+    if (blocks > h->wide_blocks) {
+      rc = ensure_idle(h);
+      if (rc) return rc;
+      if (h->wide) (void)hipFree(h->wide);
+      h->wide = nullptr;
+      h->wide_blocks = 0;
+      hipError_t e = hipMalloc((void**)&h->wide, (size_t)blocks * gc::kWideColors);
+      if (e != hipSuccess) return set_err(h, GC_ENOMEM, "wide colour flags: %s", hipGetErrorString(e));
+      h->wide_blocks = blocks;
+      h->epoch = 0;  // new memory: the next epoch (1) clears every flag
     }
     // a new epoch per call marks this call's flags; flags are cleared on the
     // first call and whenever the 8-bit epoch wraps

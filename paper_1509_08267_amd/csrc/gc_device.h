@@ -4,6 +4,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <cstdint>
 
 #include "gc_internal.h"
@@ -90,14 +91,50 @@ __device__ __forceinline__ int spec_group(const int32_t* __restrict__ colidx,
   }
 }
 
-// A vertex that has just committed colour t < kPushColors marks colour t as
-// taken for all its neighbours (row [b, e)): byte t of each neighbour's flag
-// block gets the call's epoch.  Plain byte stores: concurrent writers touch
-// different bytes or write the same value.  A group of `step` lanes.
-template <typename RP>
-__device__ __forceinline__ void push_colour(const int32_t* __restrict__ colidx, uint8_t* seen,
-                                            RP b, RP e, int t, int epoch, int gl, int step) {
-  for (RP k = b + gl; k < e; k += step) seen[(size_t)colidx[k] * kPushColors + t] = (uint8_t)epoch;
+// A vertex that has just committed colour t marks t as taken for its
+// neighbours (row [b, e)) that are still uncoloured: byte t of the
+// neighbour's flag block gets the call's epoch (t < 32), or byte t - 32 of
+// its wide block when it has one (32 <= t < 512; only vertices of degree
+// above the light bound can ever need such a colour).  Plain byte stores:
+// concurrent writers touch different bytes or write the same value.  A
+// neighbour that is already final needs nothing, which the state read skips
+// (about half of all entries).  A group of `step` lanes.
+template <typename RP, typename S>
+__device__ __forceinline__ void push_colour(const KArgs& a, const S* __restrict__ st, RP b, RP e,
+                                            int t, int epoch, int gl, int step) {
+  if (t < kPushColors) {
+    for (RP k = b + gl; k < e; k += step) {
+      const int u = a.colidx[k];
+      if (st[u] < 0) a.seen[(size_t)u * kPushColors + t] = (uint8_t)epoch;
+    }
+  } else if (t < kPushColors + kWideColors) {
+    for (RP k = b + gl; k < e; k += step) {
+      const int u = a.colidx[k];
+      const int w = a.widx[u];
+      if (w >= 0 && st[u] < 0) a.wide[(size_t)w * kWideColors + (t - kPushColors)] = (uint8_t)epoch;
+    }
+  }
+}
+
+// First colour in 32..511 not flagged in wide block w, or -1 when all are
+// taken; computed by one wavefront (every lane returns the result).
+__device__ __forceinline__ int first_free_wide(const uint8_t* wide, int w, int epoch) {
+  const int lane = lane_id();
+  constexpr int per_lane = (kWideColors + kWave - 1) / kWave;  // 8 bytes
+  int first = INT32_MAX;
+  const uint8_t* p = wide + (size_t)w * kWideColors;
+#pragma unroll
+  for (int j = 0; j < per_lane; ++j) {
+    const int c = lane * per_lane + j;
+    if (c < kWideColors && p[c] != (uint8_t)epoch && c < first) first = c;
+  }
+  // wave minimum
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const int o = __shfl_xor(first, off);
+    first = o < first ? o : first;
+  }
+  return first == INT32_MAX ? -1 : kPushColors + first;
 }
 
 // Bit c of the result is set when byte c of v's flag block equals epoch

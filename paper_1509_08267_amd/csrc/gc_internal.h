@@ -24,6 +24,7 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kTraceRounds = 65536; // rounds whose |U_r| is recorded
 constexpr int kHeavyWindow = 4096;  // LDS colour window of the block-per-vertex path (bits)
 constexpr int kPushColors = 32;     // colours tracked per vertex by pushed flags
+constexpr int kWideColors = 480;    // further colours (32..511) tracked for medium/heavy vertices
 
 // One 128-byte line per field that different blocks write, so that flags and
 // counters never share a line.
@@ -61,7 +62,9 @@ struct KArgs {
   uint8_t* seen;          // n * kPushColors: byte c of v == epoch when a neighbour of v
                           // has final colour c (plain byte stores, no atomics)
   int32_t epoch;          // epoch of this call (written to ctrl by the init kernel)
-  int32_t clear_seen;     // the init kernel zeroes `seen` (first call, epoch wrap)
+  int32_t clear_seen;     // the init kernel zeroes `seen` and `wide` (first call, epoch wrap)
+  uint8_t* wide;          // (mcount + hcount) * kWideColors flags for colours 32..511
+  const int32_t* widx;    // n: index of v's wide flag block, -1 for light vertices
   Ctrl* ctrl;
 };
 
@@ -81,7 +84,9 @@ int launch_persistent(const KArgs& a, bool rp64, int sbytes, int lanes, int max_
 int persistent_max_grid(bool rp64, int sbytes, int lanes, int* grid_out);
 int launch_classify(const void* rowptr, bool rp64, int32_t n, int32_t light_max, int32_t heavy_min,
                     int32_t* mlist, int32_t* hlist, int32_t* counts /*[3]: medium, heavy, maxdeg*/,
-                    int grid, void* stream);
+                    int32_t* widx, int grid, void* stream);
+int launch_wide_index(const int32_t* hlist, int32_t hcount, int32_t mcount, int32_t* widx,
+                      void* stream);
 int launch_validate(const void* rowptr, bool rp64, const int32_t* colidx, int32_t n, int64_t m,
                     bool sorted, int32_t* err /*[2]: code, where*/, int grid, void* stream);
 

@@ -186,7 +186,7 @@ __device__ void light_phase(const KArgs& a, long wave_gid, long nwaves, Tally& t
             if (!lose) st[vv] = (S)t;
             tl.lost += lose;
           }
-          if (push && !lose && t < kPushColors) push_colour<RP>(a.colidx, a.seen, vb, ve, t, epoch, gl, L);
+          if (push && !lose) push_colour<RP, S>(a, st, vb, ve, t, epoch, gl, L);
         }
         if (gl == 0) tl.active += 1;
       }
@@ -209,7 +209,11 @@ __device__ void medium_phase(const KArgs& a, long wave_gid, long nwaves, Tally& 
     if (PHASE == kSpec && a.push && taken_colours(a.seen, v, a.ctrl->epoch.v) != ~0u) continue;
     const RP b = rp[v], e = rp[v + 1];
     if (PHASE == kSpec) {
-      int t = spec_group<RP, S, kWave>(a.colidx, st, b, e, lane, a.push ? kPushColors : 0);
+      int t = -1;
+      if (a.push) t = first_free_wide(a.wide, a.widx[v], a.ctrl->epoch.v);
+      if (t < 0)
+        t = spec_group<RP, S, kWave>(a.colidx, st, b, e, lane,
+                                     a.push ? kPushColors + kWideColors : 0);
       if (lane == 0) st[v] = (S)~t;
     } else {
       const int t = ~s;
@@ -218,8 +222,7 @@ __device__ void medium_phase(const KArgs& a, long wave_gid, long nwaves, Tally& 
         if (!lose) st[v] = (S)t;
         tl.lost += lose;
       }
-      if (a.push && !lose && t < kPushColors)
-        push_colour<RP>(a.colidx, a.seen, b, e, t, a.ctrl->epoch.v, lane, kWave);
+      if (a.push && !lose) push_colour<RP, S>(a, st, b, e, t, a.ctrl->epoch.v, lane, kWave);
     }
     if (lane == 0) tl.active += 1;
   }
@@ -238,7 +241,18 @@ __device__ void heavy_phase(const KArgs& a, long blk, long nblk, Tally& tl, Heav
     if (s >= 0 || skip) continue;  // block-uniform
     const RP b = rp[v], e = rp[v + 1];
     if (PHASE == kSpec) {
-      int t = spec_block<RP, S>(a.colidx, st, b, e, sm, a.push ? kPushColors : 0);
+      int t = -1;
+      if (a.push) {
+        if (threadIdx.x < kWave) {
+          const int f = first_free_wide(a.wide, a.widx[v], a.ctrl->epoch.v);
+          if (threadIdx.x == 0) sm.first = f;
+        }
+        __syncthreads();
+        t = sm.first;
+        __syncthreads();
+      }
+      if (t < 0)
+        t = spec_block<RP, S>(a.colidx, st, b, e, sm, a.push ? kPushColors + kWideColors : 0);
       if (threadIdx.x == 0) st[v] = (S)~t;
     } else {
       const int t = ~s;
@@ -247,8 +261,7 @@ __device__ void heavy_phase(const KArgs& a, long blk, long nblk, Tally& tl, Heav
         if (!lose) st[v] = (S)t;
         tl.lost += lose;
       }
-      if (a.push && !lose && t < kPushColors)
-        push_colour<RP>(a.colidx, a.seen, b, e, t, a.ctrl->epoch.v, threadIdx.x, kBlock);
+      if (a.push && !lose) push_colour<RP, S>(a, st, b, e, t, a.ctrl->epoch.v, threadIdx.x, kBlock);
     }
     if (threadIdx.x == 0) tl.active += 1;
   }
@@ -343,6 +356,9 @@ __global__ void k_init(KArgs a) {
   if (a.push && a.clear_seen) {
     uint4* p = (uint4*)a.seen;  // kPushColors bytes per vertex = 2 x 16 bytes
     for (long i = tid; i < 2l * a.n; i += nth) p[i] = make_uint4(0, 0, 0, 0);
+    uint4* q = (uint4*)a.wide;  // kWideColors = 30 x 16 bytes per block
+    const long nw = (long)(a.mcount + a.hcount) * (kWideColors / 16);
+    for (long i = tid; i < nw; i += nth) q[i] = make_uint4(0, 0, 0, 0);
   }
   if (tid == 0) {
     a.ctrl->more[0].v = 0;
@@ -456,7 +472,7 @@ __global__ __launch_bounds__(kBlock) void k_persistent(KArgs a, int max_rounds) 
 // (deg >= heavy_min) vertex lists; counts[2] receives the maximum degree.
 template <typename RP>
 __global__ void k_classify(const RP* rowptr, int32_t n, int32_t light_max, int32_t heavy_min,
-                           int32_t* mlist, int32_t* hlist, int32_t* counts) {
+                           int32_t* mlist, int32_t* hlist, int32_t* counts, int32_t* widx) {
   __shared__ int sh_max;
   if (threadIdx.x == 0) sh_max = 0;
   __syncthreads();
@@ -467,10 +483,12 @@ __global__ void k_classify(const RP* rowptr, int32_t n, int32_t light_max, int32
     RP d = rowptr[v + 1] - rowptr[v];
     int di = d > (RP)INT_MAX ? INT_MAX : (int)d;
     mx = di > mx ? di : mx;
+    int w = -1;  // wide block: medium i -> i; heavy j -> mcount + j (set afterwards)
     if (di > light_max) {
       if (di >= heavy_min) hlist[atomicAdd(&counts[1], 1)] = (int)v;
-      else mlist[atomicAdd(&counts[0], 1)] = (int)v;
+      else mlist[w = atomicAdd(&counts[0], 1)] = (int)v;
     }
+    widx[v] = w;
   }
   atomicMax(&sh_max, mx);
   __syncthreads();
@@ -651,13 +669,28 @@ int launch_finish(const KArgs& a, int sbytes, int grid, void* stream) {
 }
 
 int launch_classify(const void* rowptr, bool rp64, int32_t n, int32_t light_max, int32_t heavy_min,
-                    int32_t* mlist, int32_t* hlist, int32_t* counts, int grid, void* stream) {
+                    int32_t* mlist, int32_t* hlist, int32_t* counts, int32_t* widx, int grid,
+                    void* stream) {
   if (rp64)
     hipLaunchKernelGGL(k_classify<int64_t>, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream,
-                       (const int64_t*)rowptr, n, light_max, heavy_min, mlist, hlist, counts);
+                       (const int64_t*)rowptr, n, light_max, heavy_min, mlist, hlist, counts, widx);
   else
     hipLaunchKernelGGL(k_classify<int32_t>, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream,
-                       (const int32_t*)rowptr, n, light_max, heavy_min, mlist, hlist, counts);
+                       (const int32_t*)rowptr, n, light_max, heavy_min, mlist, hlist, counts, widx);
+  return (int)hipGetLastError();
+}
+
+__global__ void k_wide_index(const int32_t* hlist, int32_t hcount, int32_t mcount, int32_t* widx) {
+  const long tid = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const long nth = (long)gridDim.x * blockDim.x;
+  for (long j = tid; j < hcount; j += nth) widx[hlist[j]] = mcount + (int)j;
+}
+
+int launch_wide_index(const int32_t* hlist, int32_t hcount, int32_t mcount, int32_t* widx,
+                      void* stream) {
+  if (hcount <= 0) return 0;
+  hipLaunchKernelGGL(k_wide_index, dim3((hcount + kBlock - 1) / kBlock), dim3(kBlock), 0,
+                     (hipStream_t)stream, hlist, hcount, mcount, widx);
   return (int)hipGetLastError();
 }
 
