@@ -7,9 +7,10 @@ no vertex is left) of the workload's graph through the C ABI (gc_color),
 with the CSR already resident in HBM.  Prints one JSON line.
 
 value        GTEPS = m / t_step (m = undirected edges, each counted once)
-roofline     the dominant kernel (speculate): algorithmic bytes of its
-             launches / their total time measured with HIP events inside the
-             captured rounds of the timed region, against 8 TB/s HBM
+roofline     the dominant round kernel (speculate or detect, by measured
+             time): algorithmic bytes of its launches / their total time
+             measured with HIP events around each launch in a second timed
+             region, against 8 TB/s HBM
 cpu_baseline the oracle (plain single-thread C) on the same graph
 """
 import argparse
@@ -63,11 +64,11 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload):
-    """HBM bytes per speculate launch from the committed rocprofv3 PMC
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC
     summary (``key: value`` lines), if it was taken on the current kernel
     source."""
-    path = os.path.join(ROOT, "profiles", f"speculate_{workload}_pmc.txt")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_pmc.txt")
     if not os.path.exists(path):
         return None
     rec = {}
@@ -152,29 +153,56 @@ def main():
     t_step = elapsed / args.steps
     gteps = g.m / t_step / 1e9
 
-    # algorithmic bytes of the speculate launches (rounds 2..R): per neighbour
-    # visit a 4-byte colidx entry and one state gather; per vertex its rowptr
-    # pair, its own state read and the tentative-colour write.  Units come
-    # from the oracle's per-round totals recorded for this workload.
+    # Algorithmic bytes per colouring of the two round kernels (rounds 2..R;
+    # round 1 has its own kernel).  Units come from the oracle's per-round
+    # totals recorded for this workload (tests/golden/workloads.json):
+    #   speculate, pull: per neighbour visit a 4-byte colidx entry and one
+    #     state gather; per uncoloured vertex its rowptr pair, its own state
+    #     read and the tentative-colour write;
+    #   speculate, push: per uncoloured vertex its 32 flag bytes, state read
+    #     and write;
+    #   detect: per lower neighbour the early-stopping scan visits, a colidx
+    #     entry and a state gather; per uncoloured vertex the rowptr pair and
+    #     state read/write; with push, every row of a vertex made final is
+    #     read with one state read per entry, plus one flag byte per entry
+    #     whose neighbour is still uncoloured.
     rp_b = 8 if rp64 else 4
-    visits = golden["sum_active_deg"] - g.nnz            # rounds >= 2
-    verts = golden["sum_active"] - g.n
-    spec_bytes_per_call = visits * (4 + sbytes) + verts * (2 * rp_b + 2 * sbytes)
+    sizes = golden["round_sizes"]
+    verts2 = golden["sum_active"] - g.n
+    visits2 = golden["sum_active_deg"] - g.nnz
+    scan2 = golden["sum_active_scan"] - (sizes[1] if len(sizes) > 1 else 0)
+    per_vertex = 2 * rp_b + 2 * sbytes
+    if algo == "push":
+        spec_bytes = verts2 * (32 + 2 * sbytes)
+    else:
+        spec_bytes = visits2 * (4 + sbytes) + verts2 * per_vertex
+    det_bytes = scan2 * (4 + sbytes) + verts2 * per_vertex
+    if algo == "push":
+        det_bytes += golden["push_rows_after_round1"] * (4 + sbytes) \
+            + golden["push_useful_after_round1"]
     spec_ms, spec_launches = prof["speculate"]
-    calls = max(1, spec_launches // max(1, rounds - 1))
-    achieved = spec_bytes_per_call * calls / (spec_ms / 1e3) / 1e9 if spec_ms > 0 else None
-    traffic = measured_traffic(args.workload)
+    det_ms, det_launches = prof["detect"]
+    kernel = "detect" if det_ms > spec_ms else "speculate"
+    k_ms, k_launches, k_bytes = ((det_ms, det_launches, det_bytes) if kernel == "detect"
+                                 else (spec_ms, spec_launches, spec_bytes))
+    calls = max(1, k_launches // max(1, rounds - 1))
+    achieved = k_bytes * calls / (k_ms / 1e3) / 1e9 if k_ms > 0 else None
+    traffic = measured_traffic(args.workload, kernel)
     roofline = {
-        "kernel": "speculate",
+        "kernel": kernel,
         "bound": "hbm",
         "achieved": round(achieved, 1) if achieved else None,
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
         "traffic": traffic,
-        "alg_bytes_per_launch": spec_bytes_per_call // max(1, rounds - 1),
-        "avg_launch_us": round(spec_ms * 1e3 / max(1, spec_launches), 2),
-        "launches": spec_launches,
+        "alg_bytes_per_launch": k_bytes // max(1, rounds - 1),
+        "avg_launch_us": round(k_ms * 1e3 / max(1, k_launches), 2),
+        "launches": k_launches,
+        "other_kernel": {"kernel": "speculate" if kernel == "detect" else "detect",
+                         "achieved": round((spec_bytes if kernel == "detect" else det_bytes) * calls
+                                           / ((spec_ms if kernel == "detect" else det_ms) / 1e3)
+                                           / 1e9, 1) if min(spec_ms, det_ms) > 0 else None},
     }
     kernels_ms_per_step = {k: round(v[0] / max(1, calls), 4) for k, v in prof.items()}
 

@@ -76,7 +76,7 @@ class RSCResult:
         self.colors = colors          # int32[n]
         self.rounds = rounds          # R
         self.round_of = round_of      # int32[n]: round in which v became final
-        self.trace = trace            # int64[R, 3]: |U_r|, sum deg, sum deg<
+        self.trace = trace            # int64[R, 4]: |U_r|, sum deg, sum deg<, early-stop scan
 
     @property
     def num_colors(self) -> int:
@@ -89,7 +89,7 @@ def rsc(rowptr, colidx, trace_cap: int = 1 << 16) -> RSCResult:
     n = rp.shape[0] - 1
     colors = np.zeros(max(n, 1), np.int32)
     round_of = np.zeros(max(n, 1), np.int32)
-    trace = np.zeros((trace_cap, 3), np.int64)
+    trace = np.zeros((trace_cap, 4), np.int64)
     R = _load().oracle_rsc(n, rp.ctypes.data, ci.ctypes.data, colors.ctypes.data,
                            round_of.ctypes.data, trace.ctypes.data, trace_cap)
     if R < 0:

@@ -66,10 +66,15 @@ static int32_t least_absent(const unsigned char *used, int64_t len) {
  * color_out[n]     final colours
  * round_out[n]     (may be NULL) the round in which each vertex's colour
  *                  became final, 1-based
- * trace[3*cap]     (may be NULL) per round r (0-based slot r-1):
- *                    trace[3(r-1)+0] = |U_r|       vertices coloured in round r
- *                    trace[3(r-1)+1] = sum of deg(v) over U_r
- *                    trace[3(r-1)+2] = sum over U_r of #neighbours u < v
+ * trace[4*cap]     (may be NULL) per round r (0-based slot r-1):
+ *                    trace[4(r-1)+0] = |U_r|       vertices coloured in round r
+ *                    trace[4(r-1)+1] = sum of deg(v) over U_r
+ *                    trace[4(r-1)+2] = sum over U_r of #neighbours u < v
+ *                    trace[4(r-1)+3] = sum over U_r of the lower neighbours a
+ *                      scan in row order examines until it meets the first
+ *                      conflicting one (all of them when there is none): the
+ *                      work of a conflict scan that stops early (a count for
+ *                      byte accounting; it does not affect the colouring)
  * returns the number of rounds R (0 when n == 0), or -1 on bad arguments
  * or allocation failure.  Rounds beyond `cap` are not traced.
  */
@@ -123,21 +128,25 @@ int64_t oracle_rsc(int64_t n, const int64_t *rowptr, const int32_t *colidx,
     /* (barrier) Phase 2 (conflict detection): v is recoloured when a
      * neighbour u of lower id, also coloured in this round, took the same
      * colour. */
-    int64_t sdeg = 0, slow = 0;
+    int64_t sdeg = 0, slow = 0, sscan = 0;
     for (int64_t i = 0; i < nU; ++i) {
       int64_t v = U[i];
       lose[v] = 0;
       sdeg += rowptr[v + 1] - rowptr[v];
       for (int64_t k = rowptr[v]; k < rowptr[v + 1]; ++k) {
         int64_t u = colidx[k];
-        if (u < v) ++slow;
+        if (u < v) {
+          ++slow;
+          if (!lose[v]) ++sscan;
+        }
         if (inU[u] && u < v && tent[u] == tent[v]) lose[v] = 1;
       }
     }
     if (trace && r <= cap) {
-      trace[3 * (r - 1) + 0] = nU;
-      trace[3 * (r - 1) + 1] = sdeg;
-      trace[3 * (r - 1) + 2] = slow;
+      trace[4 * (r - 1) + 0] = nU;
+      trace[4 * (r - 1) + 1] = sdeg;
+      trace[4 * (r - 1) + 2] = slow;
+      trace[4 * (r - 1) + 3] = sscan;
     }
     /* Colours of the vertices that did not lose become final; the losers
      * form the next round's set (kept in ascending order). */

@@ -32,8 +32,11 @@ def mex(values) -> int:
     return c
 
 
-def rsc(adj):
-    """Returns (colours, rounds, round_of)."""
+def rsc(adj, scan_counts=None):
+    """Returns (colours, rounds, round_of).  If scan_counts is a list, the
+    number of lower neighbours a row-order scan examines up to and including
+    the first conflicting one (all of them without a conflict), summed over
+    the round's vertices, is appended per round."""
     n = len(adj)
     final = {}            # v -> colour, once final
     round_of = [0] * n
@@ -44,6 +47,15 @@ def rsc(adj):
         trial = {v: mex(final[u] for u in adj[v] if u in final) for v in waiting}
         losers = {v for v in waiting
                   if any(u in waiting and u < v and trial[u] == trial[v] for u in adj[v])}
+        if scan_counts is not None:
+            total = 0
+            for v in waiting:
+                for u in adj[v]:
+                    if u < v:
+                        total += 1
+                        if u in waiting and trial[u] == trial[v]:
+                            break
+            scan_counts.append(total)
         for v in waiting - losers:
             final[v] = trial[v]
             round_of[v] = rounds

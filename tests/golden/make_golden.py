@@ -42,7 +42,7 @@ def one(name):
         colors, rounds = oracle.rsc_batch(inp.voff, inp.eoff, inp.rowptr_local, inp.colidx_local)
         rec["oracle_seconds"] = time.perf_counter() - t
         # per-round totals over all graphs (for algorithmic byte counts)
-        sa = sd = sl = 0
+        sa = sd = sl = ss = 0
         for g in range(inp.num_graphs):
             sub = inp.graph(g)
             r = oracle.rsc(sub.rowptr, sub.colidx)
@@ -50,9 +50,11 @@ def one(name):
             sa += int(r.trace[:, 0].sum())
             sd += int(r.trace[:, 1].sum())
             sl += int(r.trace[:, 2].sum())
+            ss += int(r.trace[:, 3].sum())
         rec["sum_active"] = sa
         rec["sum_active_deg"] = sd
         rec["sum_active_lower_deg"] = sl
+        rec["sum_active_scan"] = ss
         rec["colors_sha256"] = colors_sha(colors)
         rec["rounds_sha256"] = hashlib.sha256(rounds.astype(np.int64).tobytes()).hexdigest()
         rec["rounds_max"] = int(rounds.max())
@@ -76,6 +78,19 @@ def one(name):
     rec["sum_active"] = int(r.trace[:, 0].sum())
     rec["sum_active_deg"] = int(r.trace[:, 1].sum())
     rec["sum_active_lower_deg"] = int(r.trace[:, 2].sum())
+    rec["sum_active_scan"] = int(r.trace[:, 3].sum())
+    # CSR entries (v, u) whose u is still uncoloured after v's colour is
+    # final: the pushes a push-based colouring has to store
+    deg = np.diff(g.rowptr)
+    src = np.repeat(np.arange(g.n, dtype=np.int64), deg)
+    ro = r.round_of.astype(np.int64)
+    useful = ro[g.colidx.astype(np.int64)] > ro[src]
+    rec["push_useful"] = int(useful.sum())
+    # the same restricted to vertices whose colour became final after round 1
+    # (round 1 runs in its own kernel)
+    late = ro[src] >= 2
+    rec["push_rows_after_round1"] = int(late.sum())
+    rec["push_useful_after_round1"] = int((useful & late).sum())
     assert oracle.check_proper(g.rowptr, g.colidx, r.colors) == 0
     assert oracle.check_grundy(g.rowptr, g.colidx, r.colors) == 0
     t = time.perf_counter()

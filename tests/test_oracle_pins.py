@@ -254,11 +254,26 @@ def test_brute_force_chromatic_number_itself():
 def test_c_oracle_matches_python_oracle():
     for g in _random_graphs(3000, 11, seed=5):
         r = run(g)
-        col, rounds, round_of = ref_py.rsc(adj(g))
+        scans = []
+        col, rounds, round_of = ref_py.rsc(adj(g), scans)
         assert list(r.colors) == col
         assert r.rounds == rounds
         assert list(r.round_of) == round_of
+        assert list(r.trace[:, 3]) == scans
         assert list(oracle.seq(g.rowptr, g.colidx)) == ref_py.seq(adj(g))
+
+
+def test_early_stop_scan_count_bounds():
+    # the early-stop count lies between |losers with a lower neighbour| and
+    # the full lower-prefix count, and equals the latter in the last round
+    for g in list(_random_graphs(200, 12, seed=6)) + [graphgen.er(2000, 20000, 3)]:
+        r = run(g)
+        if g.n == 0:
+            continue
+        assert np.all(r.trace[:, 3] <= r.trace[:, 2])
+        losers = r.trace[1:, 0] if r.rounds > 1 else np.zeros(0, np.int64)
+        assert np.all(r.trace[:-1, 3] >= losers)
+        assert r.trace[-1, 3] == r.trace[-1, 2]
 
 
 # ------------------------------------------------------------ mutants ------
