@@ -161,16 +161,28 @@ def main():
     #     read and the tentative-colour write;
     #   speculate, push: per uncoloured vertex its 32 flag bytes, state read
     #     and write;
-    #   detect: per lower neighbour the early-stopping scan visits, a colidx
-    #     entry and a state gather; per uncoloured vertex the rowptr pair and
-    #     state read/write; with push, every row of a vertex made final is
-    #     read with one state read per entry, plus one flag byte per entry
-    #     whose neighbour is still uncoloured.
+    #   detect: per lower neighbour the early-stopping scan must visit, a
+    #     colidx entry and a state gather; per uncoloured vertex the rowptr
+    #     pair and state read/write; with push, the row entries of a vertex
+    #     made final that may still need a push are read with one state read
+    #     each, plus one flag byte per entry whose neighbour is still
+    #     uncoloured.  With sorted rows the scan and the pushes need not
+    #     revisit the leading run of lower neighbours already final (the
+    #     oracle-derived lower bounds "*_skip*"); otherwise whole prefixes
+    #     and whole rows are counted.
     rp_b = 8 if rp64 else 4
-    sizes = golden["round_sizes"]
     verts2 = golden["sum_active"] - g.n
     visits2 = golden["sum_active_deg"] - g.nnz
-    scan2 = golden["sum_active_scan"] - (sizes[1] if len(sizes) > 1 else 0)
+    skip = bool(golden.get("rows_sorted")) and "sum_active_scan_skip" in golden
+    if skip:
+        scan2 = golden["sum_active_scan_skip"]
+        push_rows = golden["push_rows_skip_after_round1"]
+    else:
+        # round 1 (every tentative colour 0) stops each scan at the first
+        # lower neighbour: one entry per vertex that has one, i.e. |U_2|
+        sizes = golden["round_sizes"]
+        scan2 = golden["sum_active_scan"] - (sizes[1] if len(sizes) > 1 else 0)
+        push_rows = golden["push_rows_after_round1"]
     per_vertex = 2 * rp_b + 2 * sbytes
     if algo == "push":
         spec_bytes = verts2 * (32 + 2 * sbytes)
@@ -178,7 +190,7 @@ def main():
         spec_bytes = visits2 * (4 + sbytes) + verts2 * per_vertex
     det_bytes = scan2 * (4 + sbytes) + verts2 * per_vertex
     if algo == "push":
-        det_bytes += golden["push_rows_after_round1"] * (4 + sbytes) \
+        det_bytes += push_rows * (4 + sbytes) \
             + golden["push_useful_after_round1"]
     spec_ms, spec_launches = prof["speculate"]
     det_ms, det_launches = prof["detect"]

@@ -66,9 +66,16 @@ enum gc_flags {
                                monotone rowptr, rowptr[0] = 0, rowptr[n] = m,
                                ids in range, no self-loops, no duplicates,
                                symmetric; rejects with GC_EINVAL           */
-  GC_ROWS_SORTED = 1u << 2  /* caller promises ascending rows; enables the
-                               early stop of the conflict scan and the
-                               O(log deg) symmetry check of GC_VALIDATE     */
+  GC_ROWS_SORTED = 1u << 2  /* caller promises strictly ascending rows;
+                               enables the round-1 closed form, the early
+                               stop of the conflict scan at the first higher
+                               neighbour, a per-vertex resume point that
+                               skips lower neighbours already final (also
+                               where a winner's pushes start), and the
+                               O(log deg) symmetry check of GC_VALIDATE,
+                               which then rejects unsorted rows; without
+                               GC_VALIDATE a broken promise gives an
+                               unspecified (possibly improper) colouring    */
 };
 
 /*
@@ -83,9 +90,13 @@ enum gc_flags {
  *   stream   stream for the set-up work (degree scan, validation)
  *
  * The graph arrays are BORROWED: they must stay allocated and unchanged
- * until gc_destroy.  The library allocates O(n) device scratch (worklists,
- * counters) and a small pinned host block; it synchronises `stream` before
- * returning.  The handle belongs to the device current at this call.
+ * until gc_destroy.  The library allocates O(n) device scratch (the state
+ * array of 1/2/4 bytes per vertex, a 4-byte resume offset per vertex,
+ * worklists and counters; on the first push-algorithm call 32 flag bytes per
+ * vertex plus 480 per vertex handled by a whole wave or workgroup, see
+ * GC_OPT_MEDIUM_DEGREE) and a small pinned host block; it synchronises
+ * `stream` before returning.  The handle belongs to the device current at
+ * this call.
  * Returns GC_OK, GC_EINVAL, GC_ENOMEM, GC_ETOOBIG or GC_EDEVICE.
  */
 int gc_create(gc_handle *out, const void *rowptr, const int32_t *colidx,
@@ -103,10 +114,11 @@ int gc_create(gc_handle *out, const void *rowptr, const int32_t *colidx,
  *               later calls queue all R rounds and return at once (R depends
  *               on the graph only).  GC_MODE_HOST reads back every round.
  *
- * One handle serves one call at a time: a second gc_color before the first
- * has been observed finished (gc_get_stats / stream sync) returns GC_EBUSY
- * when that can be detected.  Returns GC_OK, GC_EINVAL, GC_EBUSY, GC_EROUNDS
- * (GC_MODE_HOST only, when GC_OPT_MAX_ROUNDS is reached) or GC_EDEVICE.
+ * Calls on one handle are ordered: a call queued while the previous one is
+ * still running (on any stream) first waits for it on the device, since both
+ * use the handle's scratch; gc_get_stats then reports the later call.
+ * Returns GC_OK, GC_EINVAL, GC_EROUNDS (GC_MODE_HOST only, when
+ * GC_OPT_MAX_ROUNDS is reached) or GC_EDEVICE.
  */
 int gc_color(gc_handle h, int32_t *colors_out, void *stream);
 

@@ -76,6 +76,7 @@ struct gc_ctx {
   uint8_t* wide = nullptr;    // device, wide_blocks * kWideColors (push algorithm)
   int64_t wide_blocks = 0;    // blocks allocated in `wide`
   int32_t* widx = nullptr;    // device, n: wide block of each medium/heavy vertex, -1 otherwise
+  int32_t* skip = nullptr;    // device, n: final-prefix offset of each row (sorted rows)
   int epoch = 0;              // epoch of the last call's pushed flags (1..255)
   Pinned* host = nullptr;     // pinned
   int32_t mcount = 0, hcount = 0, maxdeg = 0;
@@ -182,6 +183,7 @@ static KArgs make_args(const gc_ctx* h, int32_t* colors, int light_max) {
   a.clear_seen = h->epoch == 1;
   a.wide = h->wide;
   a.widx = h->widx;
+  a.skip = h->skip;
   a.ctrl = h->ctrl;
   return a;
 }
@@ -230,6 +232,7 @@ static void free_ctx(gc_ctx* h) {
   if (h->seen) (void)hipFree(h->seen);
   if (h->wide) (void)hipFree(h->wide);
   if (h->widx) (void)hipFree(h->widx);
+  if (h->skip) (void)hipFree(h->skip);
   if (h->host) (void)hipHostFree(h->host);
   delete h;
 }
@@ -276,6 +279,7 @@ extern "C" int gc_create(gc_handle* out, const void* rowptr, const int32_t* coli
   CREATE_CHECK(hipMalloc((void**)&h->hlist, (size_t)std::max<int64_t>(n, 1) * sizeof(int32_t)));
   CREATE_CHECK(hipMalloc((void**)&h->dcounts, 8 * sizeof(int32_t)));
   CREATE_CHECK(hipMalloc((void**)&h->widx, (size_t)std::max<int64_t>(n, 1) * sizeof(int32_t)));
+  CREATE_CHECK(hipMalloc((void**)&h->skip, (size_t)std::max<int64_t>(n, 1) * sizeof(int32_t)));
   CREATE_CHECK(hipHostMalloc((void**)&h->host, sizeof(Pinned), hipHostMallocDefault));
   CREATE_CHECK(hipEventCreateWithFlags(&h->done, hipEventDisableTiming));
   memset(h->host, 0, sizeof(Pinned));

@@ -102,8 +102,21 @@ __device__ __forceinline__ int spec_group(const int32_t* __restrict__ colidx,
 template <typename RP, typename S>
 __device__ __forceinline__ void push_colour(const KArgs& a, const S* __restrict__ st, RP b, RP e,
                                             int t, int epoch, int gl, int step) {
+  // four entries per lane in flight: the neighbour ids, then their states,
+  // then the stores
   if (t < kPushColors) {
-    for (RP k = b + gl; k < e; k += step) {
+    RP k = b + gl;
+    for (; k + 3 * (RP)step < e; k += 4 * (RP)step) {
+      int u[4], s[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) u[j] = a.colidx[k + j * step];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) s[j] = st[u[j]];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (s[j] < 0) a.seen[(size_t)u[j] * kPushColors + t] = (uint8_t)epoch;
+    }
+    for (; k < e; k += step) {
       const int u = a.colidx[k];
       if (st[u] < 0) a.seen[(size_t)u * kPushColors + t] = (uint8_t)epoch;
     }
@@ -150,6 +163,61 @@ __device__ __forceinline__ uint32_t taken_colours(const uint8_t* seen, int v, in
     for (int j = 0; j < 4; ++j)
       m |= (uint32_t)(((w[i] >> (8 * j)) & 0xffu) == (uint32_t)epoch) << (4 * i + j);
   return m;
+}
+
+// Conflict scan with a skip offset (sorted rows): starting at b + *skip,
+// does a lower-id neighbour of v that is still uncoloured carry tentative
+// colour t?  Group of L lanes (gl = lane in group, gmask = the group's lanes
+// in the wave ballot, gbase = the group's first lane).  On return *skip is
+// the offset of the first still-uncoloured lower neighbour seen, or of the
+// point where the scan ended when it saw none: every lower neighbour before
+// it is final, and final colours never change, so later rounds (and the
+// winner's pushes) may start there.
+template <typename RP, typename S, int L>
+__device__ __forceinline__ bool detect_group_skip(const int32_t* __restrict__ colidx,
+                                                  const S* __restrict__ st, RP b, RP e, int v,
+                                                  int t, int gl, uint64_t gmask, int gbase,
+                                                  int* skip) {
+  int first = -1;
+  RP kb = b + *skip;
+  for (; kb < e; kb += L) {
+    const RP k = kb + gl;
+    bool act = false, conf = false, past = false;
+    if (k < e) {
+      const int u = colidx[k];
+      if (u < v) {
+        const int s = st[u];
+        act = s < 0;
+        // decode, do not test the sign: a neighbour that wins in this same
+        // pass flips ~t to t concurrently and must still count; final
+        // colours of earlier rounds never equal t
+        conf = tent_of(s) == t;
+      } else {
+        past = true;
+      }
+    } else {
+      past = true;
+    }
+    if (first < 0) {
+      const uint64_t am = (__ballot(act) & gmask) >> gbase;
+      if (am) first = (int)(kb - b) + __builtin_ctzll(am);
+    }
+    if (__ballot(conf) & gmask) {
+      // entries before the first uncoloured one are final; when none was
+      // seen (the conflicting neighbour won in this pass) the scan may
+      // restart at the conflict next round
+      if (first < 0) first = (int)(kb - b) + __builtin_ctzll((__ballot(conf) & gmask) >> gbase);
+      *skip = first;
+      return true;
+    }
+    const uint64_t pm = (__ballot(past) & gmask) >> gbase;
+    if (pm) {
+      *skip = first >= 0 ? first : (int)(kb - b) + __builtin_ctzll(pm);
+      return false;
+    }
+  }
+  *skip = first >= 0 ? first : (int)(e - b);
+  return false;
 }
 
 // Does a lower-id neighbour of v carry tentative colour t?  Group of L lanes.

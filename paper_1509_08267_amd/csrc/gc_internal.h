@@ -65,6 +65,8 @@ struct KArgs {
   int32_t clear_seen;     // the init kernel zeroes `seen` and `wide` (first call, epoch wrap)
   uint8_t* wide;          // (mcount + hcount) * kWideColors flags for colours 32..511
   const int32_t* widx;    // n: index of v's wide flag block, -1 for light vertices
+  int32_t* skip;          // n: lower neighbours before this offset of v's row are final
+                          // (sorted rows); zeroed by round 1
   Ctrl* ctrl;
 };
 

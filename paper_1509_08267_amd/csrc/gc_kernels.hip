@@ -181,12 +181,21 @@ __device__ void light_phase(const KArgs& a, long wave_gid, long nwaves, Tally& t
           if (gl == 0) st[vv] = (S)~t;
         } else {
           const int t = ~vs;
-          bool lose = detect_group<RP, S, L>(a.colidx, st, vb, ve, vv, t, gl, gmask, sorted);
+          bool lose;
+          RP pb = vb;  // winners push from here
+          if (sorted) {
+            int sk = a.skip[vv];
+            lose = detect_group_skip<RP, S, L>(a.colidx, st, vb, ve, vv, t, gl, gmask, grp * L, &sk);
+            if (gl == 0) a.skip[vv] = sk;
+            pb = vb + sk;
+          } else {
+            lose = detect_group<RP, S, L>(a.colidx, st, vb, ve, vv, t, gl, gmask, false);
+          }
           if (gl == 0) {
             if (!lose) st[vv] = (S)t;
             tl.lost += lose;
           }
-          if (push && !lose) push_colour<RP, S>(a, st, vb, ve, t, epoch, gl, L);
+          if (push && !lose) push_colour<RP, S>(a, st, pb, ve, t, epoch, gl, L);
         }
         if (gl == 0) tl.active += 1;
       }
@@ -217,12 +226,21 @@ __device__ void medium_phase(const KArgs& a, long wave_gid, long nwaves, Tally& 
       if (lane == 0) st[v] = (S)~t;
     } else {
       const int t = ~s;
-      bool lose = detect_group<RP, S, kWave>(a.colidx, st, b, e, v, t, lane, ~0ull, a.sorted != 0);
+      bool lose;
+      RP pb = b;
+      if (a.sorted) {
+        int sk = a.skip[v];
+        lose = detect_group_skip<RP, S, kWave>(a.colidx, st, b, e, v, t, lane, ~0ull, 0, &sk);
+        if (lane == 0) a.skip[v] = sk;
+        pb = b + sk;
+      } else {
+        lose = detect_group<RP, S, kWave>(a.colidx, st, b, e, v, t, lane, ~0ull, false);
+      }
       if (lane == 0) {
         if (!lose) st[v] = (S)t;
         tl.lost += lose;
       }
-      if (a.push && !lose) push_colour<RP, S>(a, st, b, e, t, a.ctrl->epoch.v, lane, kWave);
+      if (a.push && !lose) push_colour<RP, S>(a, st, pb, e, t, a.ctrl->epoch.v, lane, kWave);
     }
     if (lane == 0) tl.active += 1;
   }
@@ -332,6 +350,7 @@ __global__ __launch_bounds__(kBlock) void k_round1_sorted(KArgs a) {
     const RP b = rp[v], e = rp[v + 1];
     const bool lose = e > b && a.colidx[b] < v;
     st[v] = lose ? (S)-1 : (S)0;
+    a.skip[v] = 0;
     tl.lost += lose;
     tl.active += 1;
   }
@@ -346,7 +365,10 @@ __global__ void k_fill_tent0(KArgs a) {
   S* __restrict__ st = (S*)a.st;
   const long tid = blockIdx.x * (long)blockDim.x + threadIdx.x;
   const long nth = (long)gridDim.x * blockDim.x;
-  for (long v = tid; v < a.n; v += nth) st[v] = (S)-1;
+  for (long v = tid; v < a.n; v += nth) {
+    st[v] = (S)-1;
+    a.skip[v] = 0;
+  }
 }
 
 __global__ void k_init(KArgs a) {
@@ -450,7 +472,10 @@ __global__ __launch_bounds__(kBlock) void k_persistent(KArgs a, int max_rounds) 
     S* __restrict__ st = (S*)a.st;
     const long tid = blockIdx.x * (long)blockDim.x + threadIdx.x;
     const long nth = (long)gridDim.x * blockDim.x;
-    for (long v = tid; v < a.n; v += nth) st[v] = (S)-1;
+    for (long v = tid; v < a.n; v += nth) {
+      st[v] = (S)-1;
+      a.skip[v] = 0;
+    }
   }
   if (!grid_barrier(a.ctrl, epoch)) return;
   phase<RP, S, L, kDetect>(a, 1, blockIdx.x, gridDim.x, sm);
