@@ -220,6 +220,93 @@ __device__ __forceinline__ bool detect_group_skip(const int32_t* __restrict__ co
   return false;
 }
 
+// The scan of detect_group_skip done by one lane for its own vertex, four
+// entries in flight: neighbour ids first, then the states of the lower ones.
+// Same result and the same guarantee on *skip (every lower neighbour before
+// it is final).
+template <typename RP, typename S>
+__device__ __forceinline__ bool detect_lane_skip(const int32_t* __restrict__ colidx,
+                                                 const S* __restrict__ st, RP b, RP e, int v,
+                                                 int t, int* skip) {
+  int first = -1;
+  for (RP k = b + *skip; k < e; k += 4) {
+    int u[4], s[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) u[j] = k + j < e ? colidx[k + j] : INT32_MAX;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) s[j] = u[j] < v ? (int)st[u[j]] : 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int off = (int)(k - b) + j;
+      if (u[j] >= v) {  // past the lower prefix (or the row's end)
+        *skip = first >= 0 ? first : off;
+        return false;
+      }
+      if (first < 0 && s[j] < 0) first = off;
+      if (tent_of(s[j]) == t) {  // decoded, as in detect_group_skip
+        *skip = first >= 0 ? first : off;
+        return true;
+      }
+    }
+  }
+  *skip = first >= 0 ? first : (int)(e - b);
+  return false;
+}
+
+// The pushes of several winners of one wave, spread over all 64 lanes: lane i
+// contributes the row segment [pb, pb + len) of its own winner (len = 0 for
+// none) with colour t.  The segments are concatenated in lane order; entry j
+// of the concatenation belongs to the last lane whose exclusive prefix is
+// <= j, found by binary search over the prefixes with cross-lane reads.
+// Each lane keeps four entries in flight.  Stores as in push_colour.
+template <typename RP, typename S>
+__device__ __forceinline__ void push_flat(const KArgs& a, const S* __restrict__ st, RP pb, int len,
+                                          int t, int epoch) {
+  const int lane = lane_id();
+  int incl = len;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int y = __shfl_up(incl, off);
+    if (lane >= off) incl += y;
+  }
+  const int total = __shfl(incl, kWave - 1);
+  if (total == 0) return;  // wave-uniform
+  const int excl = incl - len;
+  for (int j0 = 0; j0 < total; j0 += 4 * kWave) {
+    int u[4], tt[4];
+    bool ok[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = j0 + q * kWave + lane;
+      ok[q] = j < total;
+      int lo = 0;
+#pragma unroll
+      for (int w = 32; w > 0; w >>= 1) {
+        const int mid = lo + w;
+        const int pm = __shfl(excl, mid < kWave ? mid : kWave - 1);
+        if (mid < kWave && pm <= j) lo = mid;
+      }
+      const RP ob = shfl_any<RP>(pb, lo);
+      const int oe = __shfl(excl, lo);
+      tt[q] = __shfl(t, lo);
+      u[q] = ok[q] ? a.colidx[ob + (j - oe)] : 0;
+    }
+    int s[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s[q] = ok[q] ? (int)st[u[q]] : 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (!ok[q] || s[q] >= 0) continue;
+      if (tt[q] < kPushColors) {
+        a.seen[(size_t)u[q] * kPushColors + tt[q]] = (uint8_t)epoch;
+      } else if (tt[q] < kPushColors + kWideColors) {
+        const int w = a.widx[u[q]];
+        if (w >= 0) a.wide[(size_t)w * kWideColors + (tt[q] - kPushColors)] = (uint8_t)epoch;
+      }
+    }
+  }
+}
+
 // Does a lower-id neighbour of v carry tentative colour t?  Group of L lanes.
 // With sorted rows the scan stops at the first neighbour id >= v.
 template <typename RP, typename S, int L>

@@ -44,6 +44,7 @@ enum { kSpec = 0, kDetect = 1 };
 
 struct HeavySmem {
   uint32_t bm[kHeavyWindow / 32];
+  uint64_t am[kWavesPerBlock], cm[kWavesPerBlock], pm[kWavesPerBlock];  // detect_block_skip
   int first;
   int active;  // per-block tallies of a detect phase
   int lost;
@@ -120,6 +121,58 @@ __device__ bool detect_block(const int32_t* __restrict__ colidx, const S* __rest
   return false;
 }
 
+// detect_group_skip for one vertex by the whole block (sorted rows): the
+// waves' ballots of "uncoloured", "conflict" and "past the lower prefix" meet
+// in LDS, and every thread reads the first set position of each.  Every
+// thread returns the same result and *skip.
+template <typename RP, typename S>
+__device__ bool detect_block_skip(const int32_t* __restrict__ colidx, const S* __restrict__ st,
+                                  RP b, RP e, int v, int t, int* skip, HeavySmem& sm) {
+  const int tid = threadIdx.x;
+  const int wv = tid / kWave;
+  int first = -1;
+  for (RP kb = b + *skip; kb < e; kb += kBlock) {
+    const RP k = kb + tid;
+    bool act = false, conf = false, past = true;
+    if (k < e) {
+      const int u = colidx[k];
+      if (u < v) {
+        const int s = st[u];
+        act = s < 0;
+        conf = tent_of(s) == t;
+        past = false;
+      }
+    }
+    const uint64_t am = __ballot(act), cm = __ballot(conf), pm = __ballot(past);
+    if (lane_id() == 0) {
+      sm.am[wv] = am;
+      sm.cm[wv] = cm;
+      sm.pm[wv] = pm;
+    }
+    __syncthreads();
+    int fa = -1, fc = -1, fp = -1;
+#pragma unroll
+    for (int i = 0; i < kWavesPerBlock; ++i) {
+      if (fa < 0 && sm.am[i]) fa = i * kWave + __builtin_ctzll(sm.am[i]);
+      if (fc < 0 && sm.cm[i]) fc = i * kWave + __builtin_ctzll(sm.cm[i]);
+      if (fp < 0 && sm.pm[i]) fp = i * kWave + __builtin_ctzll(sm.pm[i]);
+    }
+    __syncthreads();  // the masks are rewritten next iteration
+    const int off = (int)(kb - b);
+    if (first < 0 && fa >= 0) first = off + fa;
+    if (fc >= 0) {
+      *skip = first >= 0 ? first : off + fc;
+      return true;
+    }
+    if (fp >= 0) {
+      *skip = first >= 0 ? first : off + fp;
+      return false;
+    }
+  }
+  *skip = first >= 0 ? first : (int)(e - b);
+  return false;
+}
+
 // ---------------------------------------------------------- one phase --
 
 // Per-thread tallies of a phase, reduced per block at the end.
@@ -166,6 +219,27 @@ __device__ void light_phase(const KArgs& a, long wave_gid, long nwaves, Tally& t
     }
     const uint64_t am = __ballot(act);
     if (am == 0) continue;
+    if (PHASE == kDetect && sorted) {
+      // sorted rows: each lane scans for its own vertex (most scans stop
+      // within a few entries), then the chunk's winners push together
+      const int t = ~s;
+      RP pb = 0;
+      int len = 0;
+      if (act) {
+        int sk = a.skip[v];
+        const bool lose = detect_lane_skip<RP, S>(a.colidx, st, b, e, v, t, &sk);
+        a.skip[v] = sk;
+        if (!lose) {
+          st[v] = (S)t;
+          pb = b + sk;
+          len = (int)(e - pb);
+        }
+        tl.lost += lose;
+        tl.active += 1;
+      }
+      if (push) push_flat<RP, S>(a, st, pb, len, t, epoch);
+      continue;
+    }
     const int cnt = __popcll(am);
     for (int p = 0; p < cnt; p += G) {  // wave-uniform
       const int k = p + grp;
@@ -208,41 +282,58 @@ __device__ void medium_phase(const KArgs& a, long wave_gid, long nwaves, Tally& 
   const int lane = lane_id();
   const RP* __restrict__ rp = (const RP*)a.rowptr;
   S* __restrict__ st = (S*)a.st;
-  for (long i = wave_gid; i < a.mcount; i += nwaves) {
-    const int v = a.mlist[i];
-    const int s = st[v];
-    if (s >= 0) continue;  // wave-uniform
-    // with pushed flags only the vertices whose colours 0..31 are all taken
-    // scan their row here (from colour 32); the others took their colour in
-    // the light pass
-    if (PHASE == kSpec && a.push && taken_colours(a.seen, v, a.ctrl->epoch.v) != ~0u) continue;
-    const RP b = rp[v], e = rp[v + 1];
-    if (PHASE == kSpec) {
-      int t = -1;
-      if (a.push) t = first_free_wide(a.wide, a.widx[v], a.ctrl->epoch.v);
-      if (t < 0)
-        t = spec_group<RP, S, kWave>(a.colidx, st, b, e, lane,
-                                     a.push ? kPushColors + kWideColors : 0);
-      if (lane == 0) st[v] = (S)~t;
-    } else {
-      const int t = ~s;
-      bool lose;
-      RP pb = b;
-      if (a.sorted) {
-        int sk = a.skip[v];
-        lose = detect_group_skip<RP, S, kWave>(a.colidx, st, b, e, v, t, lane, ~0ull, 0, &sk);
-        if (lane == 0) a.skip[v] = sk;
-        pb = b + sk;
-      } else {
-        lose = detect_group<RP, S, kWave>(a.colidx, st, b, e, v, t, lane, ~0ull, false);
-      }
-      if (lane == 0) {
-        if (!lose) st[v] = (S)t;
-        tl.lost += lose;
-      }
-      if (a.push && !lose) push_colour<RP, S>(a, st, pb, e, t, a.ctrl->epoch.v, lane, kWave);
+  const int epoch = a.push ? a.ctrl->epoch.v : 0;
+  // A wave owns list entries wave_gid, wave_gid + nwaves, ...; it reads 64 of
+  // them and their states at once and works only on the uncoloured ones, so
+  // a round with few uncoloured medium vertices costs one load per lane, not
+  // a chain of dependent loads per entry.
+  for (long base = wave_gid; base < a.mcount; base += nwaves * kWave) {
+    const long i = base + (long)lane * nwaves;
+    int v = 0, s = 0;
+    bool act = false;
+    if (i < a.mcount) {
+      v = a.mlist[i];
+      s = st[v];
+      act = s < 0;
+      // with pushed flags only the vertices whose colours 0..31 are all
+      // taken scan their row here (from colour 32); the others took their
+      // colour in the light pass
+      if (PHASE == kSpec && a.push && act) act = taken_colours(a.seen, v, epoch) == ~0u;
     }
-    if (lane == 0) tl.active += 1;
+    uint64_t am = __ballot(act);
+    while (am) {  // wave-uniform
+      const int pos = __builtin_ctzll(am);
+      am &= am - 1;
+      const int vv = __shfl(v, pos);
+      const int vs = __shfl(s, pos);
+      const RP b = rp[vv], e = rp[vv + 1];
+      if (PHASE == kSpec) {
+        int t = -1;
+        if (a.push) t = first_free_wide(a.wide, a.widx[vv], epoch);
+        if (t < 0)
+          t = spec_group<RP, S, kWave>(a.colidx, st, b, e, lane,
+                                       a.push ? kPushColors + kWideColors : 0);
+        if (lane == 0) st[vv] = (S)~t;
+      } else {
+        const int t = ~vs;
+        bool lose;
+        RP pb = b;
+        if (a.sorted) {
+          int sk = a.skip[vv];
+          lose = detect_group_skip<RP, S, kWave>(a.colidx, st, b, e, vv, t, lane, ~0ull, 0, &sk);
+          if (lane == 0) a.skip[vv] = sk;
+          pb = b + sk;
+        } else {
+          lose = detect_group<RP, S, kWave>(a.colidx, st, b, e, vv, t, lane, ~0ull, false);
+        }
+        if (lane == 0) {
+          if (!lose) st[vv] = (S)t;
+          tl.lost += lose;
+        }
+        if (a.push && !lose) push_colour<RP, S>(a, st, pb, e, t, epoch, lane, kWave);
+      }
+      if (lane == 0) tl.active += 1;
+    }
   }
 }
 
@@ -274,12 +365,21 @@ __device__ void heavy_phase(const KArgs& a, long blk, long nblk, Tally& tl, Heav
       if (threadIdx.x == 0) st[v] = (S)~t;
     } else {
       const int t = ~s;
-      bool lose = detect_block<RP, S>(a.colidx, st, b, e, v, t, a.sorted != 0);
+      bool lose;
+      RP pb = b;
+      if (a.sorted) {
+        int sk = a.skip[v];
+        lose = detect_block_skip<RP, S>(a.colidx, st, b, e, v, t, &sk, sm);
+        if (threadIdx.x == 0) a.skip[v] = sk;
+        pb = b + sk;
+      } else {
+        lose = detect_block<RP, S>(a.colidx, st, b, e, v, t, false);
+      }
       if (threadIdx.x == 0) {
         if (!lose) st[v] = (S)t;
         tl.lost += lose;
       }
-      if (a.push && !lose) push_colour<RP, S>(a, st, b, e, t, a.ctrl->epoch.v, threadIdx.x, kBlock);
+      if (a.push && !lose) push_colour<RP, S>(a, st, pb, e, t, a.ctrl->epoch.v, threadIdx.x, kBlock);
     }
     if (threadIdx.x == 0) tl.active += 1;
   }
