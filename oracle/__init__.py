@@ -8,7 +8,8 @@ Two independent implementations of the same definitions live here:
 
 * ``oracle.c`` (loaded through ctypes): ``rsc`` follows Algorithm 1 of
   Section 3.1 with one vertex per block, ``seq`` the sequential First-Fit
-  baseline of Section 5, ``check_proper`` / ``check_grundy`` the properties
+  baseline of Section 5, ``seq_rounds`` the rounds in which an id-priority
+  schedule reproduces it, ``check_proper`` / ``check_grundy`` the properties
   of Section 2.1 and Lemma 1 (Section 4);
 * ``ref_py`` (pure Python, tiny graphs): the same definitions written again
   from the paper, used to cross-check the C code, plus a brute-force
@@ -53,6 +54,8 @@ def _load():
         lib.oracle_rsc.argtypes = [i64, p, p, p, p, p, i64]
         lib.oracle_seq.restype = ctypes.c_int
         lib.oracle_seq.argtypes = [i64, p, p, p]
+        lib.oracle_seq_rounds.restype = i64
+        lib.oracle_seq_rounds.argtypes = [i64, p, p, p]
         lib.oracle_check_proper.restype = i64
         lib.oracle_check_proper.argtypes = [i64, p, p, p]
         lib.oracle_check_grundy.restype = i64
@@ -105,6 +108,18 @@ def seq(rowptr, colidx) -> np.ndarray:
     if _load().oracle_seq(n, rp.ctypes.data, ci.ctypes.data, colors.ctypes.data) != 0:
         raise ValueError("oracle_seq rejected its input")
     return colors[:n]
+
+
+def seq_rounds(rowptr, colidx):
+    """(R, round_of) of the id-priority schedule that reproduces ``seq``:
+    round_of[v] = vertices on the longest id-increasing path ending at v."""
+    rp, ci = _csr(rowptr, colidx)
+    n = rp.shape[0] - 1
+    rounds = np.zeros(max(n, 1), np.int32)
+    R = _load().oracle_seq_rounds(n, rp.ctypes.data, ci.ctypes.data, rounds.ctypes.data)
+    if R < 0:
+        raise ValueError("oracle_seq_rounds rejected its input")
+    return int(R), rounds[:n]
 
 
 def check_proper(rowptr, colidx, colors) -> int:

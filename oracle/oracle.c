@@ -39,6 +39,9 @@
  *
  *   oracle_seq  -- the sequential First-Fit baseline of Section 5 (vertex
  *                  order 0, 1, ..., n-1; the paper does not state the order).
+ *   oracle_seq_rounds -- the rounds in which an id-priority schedule gives
+ *                  every vertex that same colour: the longest id-increasing
+ *                  path ending at each vertex.
  *
  *   oracle_check_* -- what the problem statement (Section 2.1) and Lemma 1
  *                  (Section 4) fix: a proper colouring, and First-Fit's
@@ -196,6 +199,31 @@ int oracle_seq(int64_t n, const int64_t *rowptr, const int32_t *colidx,
   }
   free(used);
   return 0;
+}
+
+/* Rounds of the id-priority schedule that reproduces oracle_seq in parallel
+ * (a vertex takes its First-Fit colour in the first round in which all of its
+ * lower-id neighbours are coloured; the sequential baseline of Section 5 run
+ * as a dependency schedule).  By definition, the round of v is
+ *     depth(v) = 1 + max{ depth(u) : u in N(v), u < v }   (1 when there is none),
+ * the number of vertices on the longest id-increasing path ending at v; it is
+ * computed in id order, where every depth(u) needed is already known.
+ * round_out[n] receives depth(v); returns R = max depth (0 when n == 0), or
+ * -1 on bad arguments. */
+int64_t oracle_seq_rounds(int64_t n, const int64_t *rowptr, const int32_t *colidx,
+                          int32_t *round_out) {
+  if (n < 0 || (n > 0 && (!rowptr || !round_out))) return -1;
+  int64_t R = 0;
+  for (int64_t v = 0; v < n; ++v) {
+    int32_t d = 0;
+    for (int64_t k = rowptr[v]; k < rowptr[v + 1]; ++k) {
+      int64_t u = colidx[k];
+      if (u < v && round_out[u] > d) d = round_out[u];
+    }
+    round_out[v] = d + 1;
+    if (d + 1 > R) R = d + 1;
+  }
+  return R;
 }
 
 /* Number of CSR entries (v, u) with color[v] == color[u], plus the number of

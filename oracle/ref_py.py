@@ -9,6 +9,9 @@ passages, so that a slip in one is caught by the other:
   that took the same colour this round the higher id is recoloured; repeat.
   Neighbours still waiting for a colour forbid nothing.
 * ``seq`` -- sequential First Fit in id order (Section 5 baseline).
+* ``seq_schedule`` -- the same colours by rounds: a vertex is coloured once
+  its lower neighbours are; ``longest_increasing_path`` gives its round by
+  enumeration.
 * ``chromatic_number`` -- brute force over all colourings, for n <= 10,
   the quantity the paper's objective minimises (Section 2.1).
 
@@ -69,6 +72,45 @@ def seq(adj):
     for v in range(n):
         col[v] = mex(col[u] for u in adj[v] if u < v)
     return col
+
+
+def longest_increasing_path(adj):
+    """Per vertex v, the most vertices on a path whose ids increase and end
+    at v, by exhaustive depth-first enumeration of such paths (tiny graphs)."""
+    n = len(adj)
+    best = [1] * n
+
+    def walk(v, length):
+        if length > best[v]:
+            best[v] = length
+        for u in adj[v]:
+            if u > v:
+                walk(u, length + 1)
+
+    for v in range(n):
+        walk(v, 1)
+    return best
+
+
+def seq_schedule(adj):
+    """The id-priority schedule run round by round: in each round every
+    uncoloured vertex whose lower neighbours are all coloured (at the round's
+    start) takes the least colour absent among them.  Returns (colours,
+    rounds, round_of)."""
+    n = len(adj)
+    col = [None] * n
+    round_of = [0] * n
+    waiting = set(range(n))
+    r = 0
+    while waiting:
+        r += 1
+        ready = [v for v in waiting if all(col[u] is not None for u in adj[v] if u < v)]
+        picks = {v: mex(col[u] for u in adj[v] if u < v) for v in ready}
+        for v, c in picks.items():
+            col[v] = c
+            round_of[v] = r
+        waiting -= set(ready)
+    return col, r, round_of
 
 
 def is_proper(adj, col) -> bool:

@@ -144,6 +144,59 @@ def _csr(g):
     return g.rowptr, g.colidx
 
 
+# ------------------------------- id-priority schedule of SEQ (its rounds) --
+
+def test_seq_rounds_closed_forms():
+    # a path in natural order is one increasing path: round v + 1 for v
+    R, ro = oracle.seq_rounds(*_csr(graphgen.path(9)))
+    assert R == 9 and list(ro) == list(range(1, 10))
+    # K_n: the ids themselves form the longest increasing path
+    R, ro = oracle.seq_rounds(*_csr(graphgen.complete(7)))
+    assert R == 7 and list(ro) == list(range(1, 8))
+    # star: leaves before a high centre, or a low centre before its leaves
+    R, ro = oracle.seq_rounds(*_csr(graphgen.star(5, centre=5)))
+    assert R == 2 and list(ro) == [1] * 5 + [2]
+    R, ro = oracle.seq_rounds(*_csr(graphgen.star(5, centre=0)))
+    assert R == 2 and list(ro) == [1] + [2] * 5
+    # no edges: one round; no vertices: none
+    assert oracle.seq_rounds(*_csr(graphgen.empty(4)))[0] == 1
+    assert oracle.seq_rounds(*_csr(graphgen.empty(0)))[0] == 0
+    # path relabelled so the ids alternate low/high: every vertex is a local
+    # extreme, two rounds
+    p = graphgen.relabel(graphgen.path(8), [0, 4, 1, 5, 2, 6, 3, 7])
+    assert oracle.seq_rounds(*_csr(p))[0] == 2
+
+
+def test_seq_rounds_equal_longest_increasing_path_by_enumeration():
+    for g in _random_graphs(500, 9, seed=21):
+        R, ro = oracle.seq_rounds(g.rowptr, g.colidx)
+        best = ref_py.longest_increasing_path(adj(g))
+        assert list(ro) == best
+        assert R == (max(best) if best else 0)
+
+
+def test_seq_schedule_reproduces_sequential_first_fit():
+    # the round-by-round schedule colours exactly like SEQ, in depth rounds
+    for g in list(_random_graphs(300, 11, seed=22)) + [graphgen.er(300, 2000, 4)]:
+        col, R, round_of = ref_py.seq_schedule(adj(g))
+        assert col == list(oracle.seq(g.rowptr, g.colidx))
+        R2, ro = oracle.seq_rounds(g.rowptr, g.colidx)
+        assert R == R2 and round_of == list(ro)
+
+
+def test_seq_rounds_pins_reject_a_reversed_dependency():
+    # a plausible slip: depending on higher-id neighbours instead
+    def wrong(g):
+        n = g.n
+        d = [0] * n
+        a = adj(g)
+        for v in reversed(range(n)):
+            d[v] = 1 + max([d[u] for u in a[v] if u > v], default=0)
+        return d
+    g = graphgen.star(5, centre=0)
+    assert wrong(g) != list(oracle.seq_rounds(*_csr(g))[1])
+
+
 # ------------------------------------------------------ properties (random) --
 
 def _random_graphs(count, nmax, seed):
