@@ -46,10 +46,15 @@ struct Pinned {  // read-back area in pinned host memory
   int32_t pad1[3];
 };
 
-struct Captured {  // one instantiated chunk of K rounds
+// One instantiated chunk of K rounds.  The graph holds the kernel arguments
+// and grid of its capture, so it is replayed only while everything the round
+// kernels read from them is unchanged (options and reallocations change the
+// degree lists, the flag blocks and the grid).
+struct Captured {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  int k = 0, lanes = 0, light = 0, push = 0;
+  int k = 0, lanes = 0, grid = 0;
+  KArgs args{};
 };
 
 // Kernel kinds reported by gc_get_profile.
@@ -154,15 +159,19 @@ static int light_max_of(const gc_ctx* h, int L) {
   return std::max(8 * L, 64);
 }
 
+// Colours never exceed the degree; the largest value of the type stays unused
+// so that the smallest can mark "waiting" under GC_ALGO_SEQ.
 static int state_bytes(int32_t maxdeg) {
-  if (maxdeg <= 127) return 1;
-  if (maxdeg <= 32767) return 2;
+  if (maxdeg <= 126) return 1;
+  if (maxdeg <= 32766) return 2;
   return 4;
 }
 
 static bool use_push(const gc_ctx* h) {
   return h->algorithm == GC_ALGO_PUSH || h->algorithm == GC_ALGO_AUTO;
 }
+
+static bool use_seq(const gc_ctx* h) { return h->algorithm == GC_ALGO_SEQ; }
 
 static KArgs make_args(const gc_ctx* h, int32_t* colors, int light_max) {
   KArgs a{};
@@ -178,6 +187,7 @@ static KArgs make_args(const gc_ctx* h, int32_t* colors, int light_max) {
   a.hcount = h->hcount;
   a.sorted = (h->flags & GC_ROWS_SORTED) != 0;
   a.push = use_push(h) ? 1 : 0;
+  a.seq = use_seq(h) ? 1 : 0;
   a.seen = h->seen;
   a.epoch = h->epoch;
   a.clear_seen = h->epoch == 1;
@@ -372,13 +382,22 @@ static int capture(gc_ctx* h, Captured& c, const KArgs& a, int L, int K) {
   c.exec = x;
   c.k = K;
   c.lanes = L;
-  c.light = a.light_max;
-  c.push = a.push;
+  c.grid = grid_of(h);
+  c.args = a;
   return GC_OK;
 }
 
-static bool usable(const Captured& c, int K, int L, int light, int push) {
-  return c.exec && c.k == K && c.lanes == L && c.light == light && c.push == push;
+// Fields of KArgs that the captured round kernels read (the call's epoch and
+// output pointer reach them through the control block and the finish kernel,
+// which are launched outside the graph).
+static bool usable(const Captured& c, int K, int L, int grid, const KArgs& a) {
+  const KArgs& b = c.args;
+  return c.exec && c.k == K && c.lanes == L && c.grid == grid && b.rowptr == a.rowptr &&
+         b.colidx == a.colidx && b.st == a.st && b.n == a.n && b.light_max == a.light_max &&
+         b.mlist == a.mlist && b.mcount == a.mcount && b.hlist == a.hlist &&
+         b.hcount == a.hcount && b.sorted == a.sorted && b.push == a.push && b.seq == a.seq &&
+         b.seen == a.seen && b.wide == a.wide && b.widx == a.widx && b.skip == a.skip &&
+         b.ctrl == a.ctrl;
 }
 
 static float elapsed(hipEvent_t a, hipEvent_t b) {
@@ -512,7 +531,7 @@ extern "C" int gc_color(gc_handle h, int32_t* colors_out, void* stream) {
       // R is known: queue rounds 2..R in one captured chunk, no read-back.
       const int K = (int)h->known_rounds - 1;
       if (K > 0) {
-        if (!usable(h->exact, K, L, light, a.push)) {
+        if (!usable(h->exact, K, L, grid, a)) {
           rc = capture(h, h->exact, a, L, K);
           if (rc) return rc;
         }
@@ -539,7 +558,7 @@ extern "C" int gc_color(gc_handle h, int32_t* colors_out, void* stream) {
           }
           r = upto;
         } else if (mode == GC_MODE_GRAPH) {
-          if (!usable(h->chunk, K, L, light, a.push)) {
+          if (!usable(h->chunk, K, L, grid, a)) {
             rc = capture(h, h->chunk, a, L, K);
             if (rc) return rc;
           }
@@ -655,7 +674,11 @@ extern "C" int gc_set_option(gc_handle h, int option, int64_t value) {
       h->persist_per_cu = (int)value;
       return GC_OK;
     case GC_OPT_ALGORITHM:
-      if (value < GC_ALGO_AUTO || value > GC_ALGO_PUSH) break;
+      if (value < GC_ALGO_AUTO || value > GC_ALGO_SEQ) break;
+      // the round count R is a property of the graph and of the colouring
+      // computed: switching between the speculative colouring and SEQ
+      // forgets it
+      if ((value == GC_ALGO_SEQ) != use_seq(h)) h->known_rounds = 0;
       h->algorithm = (int)value;
       return GC_OK;
     case GC_OPT_PROFILE:
@@ -688,7 +711,9 @@ extern "C" int gc_get_option(gc_handle h, int option, int64_t* value) {
     case GC_OPT_PERSISTENT_BLOCKS_PER_CU: *value = h->persist_per_cu; return GC_OK;
     case GC_OPT_STATE_BYTES: *value = h->sbytes; return GC_OK;
     case GC_OPT_PROFILE: *value = h->profile; return GC_OK;
-    case GC_OPT_ALGORITHM: *value = use_push(h) ? GC_ALGO_PUSH : GC_ALGO_PULL; return GC_OK;
+    case GC_OPT_ALGORITHM:
+      *value = use_seq(h) ? GC_ALGO_SEQ : use_push(h) ? GC_ALGO_PUSH : GC_ALGO_PULL;
+      return GC_OK;
     default: return set_err(h, GC_EINVAL, "gc_get_option: unknown option %d", option);
   }
 }

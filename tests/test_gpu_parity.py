@@ -214,7 +214,7 @@ def test_other_stream(gc):
 def test_state_widths(gc):
     # the working state is 1, 2 or 4 bytes by maximum degree; all give the
     # oracle's bits
-    cases = [(graphgen.star(127, 0), 1), (graphgen.star(128, 0), 2),
+    cases = [(graphgen.star(126, 0), 1), (graphgen.star(127, 0), 2),
              (graphgen.complete(300), 2), (graphgen.star(40000, 7), 4)]
     for g, width in cases:
         rp, ci = _dev(g)
@@ -339,3 +339,24 @@ def test_workload_rmat(gc):
     g, col = _full(gc, "rmat22_ef16", algorithm="push")
     assert oracle.check_proper(g.rowptr, g.colidx, col) == 0
     assert oracle.check_grundy(g.rowptr, g.colidx, col) == 0
+
+
+def test_options_changed_between_calls_on_one_handle(gc):
+    # a captured round graph carries its degree lists, flag blocks and grid:
+    # every option change between calls must give the oracle's bits
+    g = graphgen.rmat(14, 16, seed=3)
+    ref = oracle.rsc(g.rowptr, g.colidx)
+    rp, ci = _dev(g, rp64=True)
+    steps = [{}, {"heavy_degree": 1024}, {"heavy_degree": 16384}, {"blocks_per_cu": 2},
+             {"medium_degree": 32}, {"lanes": 4}, {"heavy_degree": 256, "medium_degree": 16},
+             {"blocks_per_cu": 16}, {"algorithm": "pull"}, {"heavy_degree": 2048}]
+    with gc.Graph(rp, ci, mode="graph") as G:
+        for opts in steps:
+            for k, v in opts.items():
+                G.set(k, v)
+            for _ in range(2):
+                print(f"[case] live options {opts}", flush=True)
+                out = G.color()
+                r, _ = G.stats()
+                assert r == ref.rounds, opts
+                assert np.array_equal(out.cpu().numpy(), ref.colors), opts
