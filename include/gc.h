@@ -160,7 +160,7 @@ enum gc_option {
   GC_OPT_PERSISTENT_BLOCKS_PER_CU = 11, /* workgroups per CU of the persistent kernel,
                                 1..6 (4); more are not reliably co-resident   */
   GC_OPT_STATE_BYTES = 12,   /* (get only) bytes per vertex of the working state:
-                                1 if max degree <= 127, 2 if <= 32767, else 4 */
+                                1 if max degree <= 126, 2 if <= 32766, else 4 */
   GC_OPT_PROFILE = 13,       /* 1: time the kernels of each call with HIP events
                                 recorded on the call's stream; once R is known
                                 the rounds are launched directly (not as a
@@ -168,18 +168,27 @@ enum gc_option {
                                 kernel; read with gc_get_profile           */
   GC_OPT_ALGORITHM = 14      /* enum gc_algorithm (default GC_ALGO_AUTO)           */
 };
-/* How speculation learns the final colours of a vertex's neighbours.  Both
- * give the same colouring. */
+/* The colouring to compute.  AUTO, PULL and PUSH compute the same colouring
+ * (round-synchronous speculation, Algorithm 1 of Section 3.1 with every vertex
+ * its own block) and differ in how speculation learns the final colours of a
+ * vertex's neighbours.  SEQ computes another one: the sequential First-Fit
+ * colouring in id order (the baseline of Section 5). */
 enum gc_algorithm {
   GC_ALGO_AUTO = 0,  /* currently PUSH                                             */
   GC_ALGO_PULL = 1,  /* each round, each uncoloured vertex gathers the state of all
                         its neighbours and builds its forbidden-colour mask        */
-  GC_ALGO_PUSH = 2   /* a vertex whose colour c < 32 becomes final marks colour c
+  GC_ALGO_PUSH = 2,  /* a vertex whose colour c < 32 becomes final marks colour c
                         as taken in a 32-byte flag block of each neighbour (one
                         plain byte store per CSR entry over the whole colouring,
                         no atomics); speculation reads its 32 flags and scans its
                         row only when colours 0..31 are all taken.  32 bytes per
                         vertex of device memory                                 */
+  GC_ALGO_SEQ = 3    /* sequential First Fit in id order, computed in rounds: a
+                        vertex takes the least colour absent from its lower-id
+                        neighbours in the first round in which all of them are
+                        coloured.  The colours equal the sequential ones bit for
+                        bit; R is the number of vertices on the longest path
+                        whose ids increase                                      */
 };
 enum gc_mode {
   GC_MODE_AUTO = 0,       /* currently GRAPH                                      */

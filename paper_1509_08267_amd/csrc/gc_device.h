@@ -307,6 +307,50 @@ __device__ __forceinline__ void push_flat(const KArgs& a, const S* __restrict__ 
   }
 }
 
+// The state value of a vertex that is not yet ready under the id-priority
+// schedule: the smallest value of the state type (colours and ~colour stay
+// above it, since colours never exceed the degree and the state width
+// leaves one value spare).
+template <typename S>
+__device__ __forceinline__ int waiting_state() {
+  return sizeof(S) == 1 ? -128 : sizeof(S) == 2 ? -32768 : INT32_MIN;
+}
+
+// Is every lower-id neighbour of v final?  Group of L lanes.  With sorted
+// rows the scan starts at *skip, stops at the first id >= v, and leaves in
+// *skip the offset of the first lower neighbour that is not final (or where
+// it ended): every lower neighbour before it is final for good.
+template <typename RP, typename S, int L>
+__device__ __forceinline__ bool ready_group(const int32_t* __restrict__ colidx,
+                                            const S* __restrict__ st, RP b, RP e, int v, int gl,
+                                            uint64_t gmask, int gbase, bool sorted, int* skip) {
+  for (RP kb = b + (sorted ? *skip : 0); kb < e; kb += L) {
+    const RP k = kb + gl;
+    bool wait = false, past = false;
+    if (k < e) {
+      const int u = colidx[k];
+      if (u < v) wait = st[u] < 0;
+      else past = true;
+    } else {
+      past = true;
+    }
+    const uint64_t wm = (__ballot(wait) & gmask) >> gbase;
+    if (wm) {
+      if (sorted) *skip = (int)(kb - b) + __builtin_ctzll(wm);
+      return false;
+    }
+    if (sorted) {
+      const uint64_t pm = (__ballot(past) & gmask) >> gbase;
+      if (pm) {
+        *skip = (int)(kb - b) + __builtin_ctzll(pm);
+        return true;
+      }
+    }
+  }
+  if (sorted) *skip = (int)(e - b);
+  return true;
+}
+
 // Does a lower-id neighbour of v carry tentative colour t?  Group of L lanes.
 // With sorted rows the scan stops at the first neighbour id >= v.
 template <typename RP, typename S, int L>

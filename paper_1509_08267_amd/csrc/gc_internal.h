@@ -59,6 +59,8 @@ struct KArgs {
   int32_t hcount;
   int32_t sorted;         // rows ascending: the conflict scan may stop early
   int32_t push;           // forbidden colours pushed by committing neighbours
+  int32_t seq;            // id-priority First Fit: speculate picks the vertices whose lower
+                          // neighbours are all final, detect commits them (no conflicts)
   uint8_t* seen;          // n * kPushColors: byte c of v == epoch when a neighbour of v
                           // has final colour c (plain byte stores, no atomics)
   int32_t epoch;          // epoch of this call (written to ctrl by the init kernel)

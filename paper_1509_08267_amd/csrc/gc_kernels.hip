@@ -193,9 +193,23 @@ __device__ void light_phase(const KArgs& a, long wave_gid, long nwaves, Tally& t
   const bool sorted = a.sorted != 0;
   const bool push = a.push != 0;
   const int epoch = push ? a.ctrl->epoch.v : 0;
+  const bool seq = a.seq != 0;
   const long nchunks = ((long)a.n + kWave - 1) / kWave;
   for (long ch = wave_gid; ch < nchunks; ch += nwaves) {
     const int v = (int)(ch * kWave) + lane;
+    if (PHASE == kDetect && seq) {
+      // id-priority schedule: every vertex picked this round (any degree
+      // class) commits; the others keep waiting
+      if (v < a.n) {
+        const int s0 = st[v];
+        if (s0 < 0) {
+          if (s0 != waiting_state<S>()) st[v] = (S)~s0;
+          else tl.lost += 1;
+          tl.active += 1;
+        }
+      }
+      continue;
+    }
     bool act = false;
     int s = 0;
     RP b = 0, e = 0;
@@ -250,7 +264,19 @@ __device__ void light_phase(const KArgs& a, long wave_gid, long nwaves, Tally& t
       const int vs = shfl_any<int32_t>(s, pos);
       const int vv = (int)(ch * kWave) + pos;
       if (valid) {  // group-uniform
-        if (PHASE == kSpec) {
+        if (PHASE == kSpec && seq) {
+          // ready once every lower neighbour is final; then the least colour
+          // absent from the final neighbours is the least absent from the
+          // lower ones (a higher neighbour cannot be final before v)
+          int sk = sorted ? a.skip[vv] : 0;
+          const bool ready =
+              ready_group<RP, S, L>(a.colidx, st, vb, ve, vv, gl, gmask, grp * L, sorted, &sk);
+          if (sorted && gl == 0) a.skip[vv] = sk;
+          if (ready) {
+            const int t = spec_group<RP, S, L>(a.colidx, st, vb, ve, gl, 0);
+            if (gl == 0) st[vv] = (S)~t;
+          }
+        } else if (PHASE == kSpec) {
           int t = spec_group<RP, S, L>(a.colidx, st, vb, ve, gl, push ? kPushColors : 0);
           if (gl == 0) st[vv] = (S)~t;
         } else {
@@ -282,6 +308,7 @@ __device__ void medium_phase(const KArgs& a, long wave_gid, long nwaves, Tally& 
   const int lane = lane_id();
   const RP* __restrict__ rp = (const RP*)a.rowptr;
   S* __restrict__ st = (S*)a.st;
+  if (PHASE == kDetect && a.seq) return;  // the light pass commits every vertex
   const int epoch = a.push ? a.ctrl->epoch.v : 0;
   // A wave owns list entries wave_gid, wave_gid + nwaves, ...; it reads 64 of
   // them and their states at once and works only on the uncoloured ones, so
@@ -307,7 +334,16 @@ __device__ void medium_phase(const KArgs& a, long wave_gid, long nwaves, Tally& 
       const int vv = __shfl(v, pos);
       const int vs = __shfl(s, pos);
       const RP b = rp[vv], e = rp[vv + 1];
-      if (PHASE == kSpec) {
+      if (PHASE == kSpec && a.seq) {
+        int sk = a.sorted ? a.skip[vv] : 0;
+        const bool ready = ready_group<RP, S, kWave>(a.colidx, st, b, e, vv, lane, ~0ull, 0,
+                                                     a.sorted != 0, &sk);
+        if (a.sorted && lane == 0) a.skip[vv] = sk;
+        if (ready) {
+          const int t = spec_group<RP, S, kWave>(a.colidx, st, b, e, lane, 0);
+          if (lane == 0) st[vv] = (S)~t;
+        }
+      } else if (PHASE == kSpec) {
         int t = -1;
         if (a.push) t = first_free_wide(a.wide, a.widx[vv], epoch);
         if (t < 0)
@@ -337,8 +373,29 @@ __device__ void medium_phase(const KArgs& a, long wave_gid, long nwaves, Tally& 
   }
 }
 
+// Is every lower-id neighbour of v final?  Whole block (heavy vertices).
+template <typename RP, typename S>
+__device__ bool ready_block(const int32_t* __restrict__ colidx, const S* __restrict__ st,
+                            RP b, RP e, int v, bool sorted) {
+  for (RP kb = b; kb < e; kb += kBlock) {
+    const RP k = kb + threadIdx.x;
+    int wait = 0, past = 1;
+    if (k < e) {
+      const int u = colidx[k];
+      if (u < v) {
+        wait = st[u] < 0;
+        past = 0;
+      }
+    }
+    if (__syncthreads_or(wait)) return false;
+    if (sorted && __syncthreads_or(past)) return true;
+  }
+  return true;
+}
+
 template <typename RP, typename S, int PHASE>
 __device__ void heavy_phase(const KArgs& a, long blk, long nblk, Tally& tl, HeavySmem& sm) {
+  if (PHASE == kDetect && a.seq) return;  // the light pass commits every vertex
   const RP* __restrict__ rp = (const RP*)a.rowptr;
   S* __restrict__ st = (S*)a.st;
   for (long i = blk; i < a.hcount; i += nblk) {
@@ -349,7 +406,12 @@ __device__ void heavy_phase(const KArgs& a, long blk, long nblk, Tally& tl, Heav
     __syncthreads();  // the commit below happens after every thread read s
     if (s >= 0 || skip) continue;  // block-uniform
     const RP b = rp[v], e = rp[v + 1];
-    if (PHASE == kSpec) {
+    if (PHASE == kSpec && a.seq) {
+      if (ready_block<RP, S>(a.colidx, st, b, e, v, a.sorted != 0)) {
+        const int t = spec_block<RP, S>(a.colidx, st, b, e, sm, 0);
+        if (threadIdx.x == 0) st[v] = (S)~t;
+      }
+    } else if (PHASE == kSpec) {
       int t = -1;
       if (a.push) {
         if (threadIdx.x < kWave) {
@@ -465,8 +527,9 @@ __global__ void k_fill_tent0(KArgs a) {
   S* __restrict__ st = (S*)a.st;
   const long tid = blockIdx.x * (long)blockDim.x + threadIdx.x;
   const long nth = (long)gridDim.x * blockDim.x;
+  const S init = (S)(a.seq ? waiting_state<S>() : -1);
   for (long v = tid; v < a.n; v += nth) {
-    st[v] = (S)-1;
+    st[v] = init;
     a.skip[v] = 0;
   }
 }
@@ -572,12 +635,17 @@ __global__ __launch_bounds__(kBlock) void k_persistent(KArgs a, int max_rounds) 
     S* __restrict__ st = (S*)a.st;
     const long tid = blockIdx.x * (long)blockDim.x + threadIdx.x;
     const long nth = (long)gridDim.x * blockDim.x;
+    const S init = (S)(a.seq ? waiting_state<S>() : -1);
     for (long v = tid; v < a.n; v += nth) {
-      st[v] = (S)-1;
+      st[v] = init;
       a.skip[v] = 0;
     }
   }
   if (!grid_barrier(a.ctrl, epoch)) return;
+  if (a.seq) {
+    phase<RP, S, L, kSpec>(a, 1, blockIdx.x, gridDim.x, sm);
+    if (!grid_barrier(a.ctrl, epoch)) return;
+  }
   phase<RP, S, L, kDetect>(a, 1, blockIdx.x, gridDim.x, sm);
   if (!grid_barrier(a.ctrl, epoch)) return;
   for (int r = 2; max_rounds <= 0 || r <= max_rounds; ++r) {
@@ -694,13 +762,17 @@ static int launch_round_t(const KArgs& a, int phase_id, int round, bool from_bas
 
 template <typename RP, typename S, int L>
 static int launch_round1_t(const KArgs& a, int grid, hipStream_t s) {
-  if (a.sorted && !a.push) {
+  if (a.sorted && !a.push && !a.seq) {
     hipLaunchKernelGGL((k_round1_sorted<RP, S>), dim3(grid), dim3(kBlock), 0, s, a);
     return (int)hipGetLastError();
   }
   hipLaunchKernelGGL((k_fill_tent0<S>), dim3(grid), dim3(kBlock), 0, s, a);
   int rc = (int)hipGetLastError();
   if (rc) return rc;
+  if (a.seq) {  // round 1 picks the vertices with no lower neighbour
+    rc = launch_round_t<RP, S, L>(a, kSpec, 1, false, grid, s);
+    if (rc) return rc;
+  }
   return launch_round_t<RP, S, L>(a, kDetect, 1, false, grid, s);
 }
 

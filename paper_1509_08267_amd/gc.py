@@ -29,8 +29,9 @@ GC_ROWPTR_I64, GC_VALIDATE, GC_ROWS_SORTED = 1, 2, 4
  GC_OPT_CHUNK_ROUNDS, GC_OPT_MEDIUM_DEGREE, GC_OPT_MAX_DEGREE, GC_OPT_MEDIUM_COUNT,
  GC_OPT_HEAVY_COUNT, GC_OPT_PERSISTENT_BLOCKS_PER_CU, GC_OPT_STATE_BYTES,
  GC_OPT_PROFILE, GC_OPT_ALGORITHM) = range(1, 15)
-GC_ALGO_AUTO, GC_ALGO_PULL, GC_ALGO_PUSH = range(3)
-ALGORITHMS = {"auto": GC_ALGO_AUTO, "pull": GC_ALGO_PULL, "push": GC_ALGO_PUSH}
+GC_ALGO_AUTO, GC_ALGO_PULL, GC_ALGO_PUSH, GC_ALGO_SEQ = range(4)
+ALGORITHMS = {"auto": GC_ALGO_AUTO, "pull": GC_ALGO_PULL, "push": GC_ALGO_PUSH,
+              "seq": GC_ALGO_SEQ}
 PROFILE_KINDS = ("round1", "speculate", "detect", "finish")
 # enum gc_mode
 GC_MODE_AUTO, GC_MODE_HOST, GC_MODE_CHUNKED, GC_MODE_PERSISTENT, GC_MODE_GRAPH = range(5)
