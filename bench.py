@@ -35,7 +35,12 @@ def parse():
     p.add_argument("--workload", default="er_1m_16m")
     p.add_argument("--mode", default="graph")
     p.add_argument("--algorithm", default="auto", choices=["auto", "pull", "push"])
-    p.add_argument("--lanes", type=int, default=0)
+    p.add_argument("--lanes", type=int, default=0,
+                   help="fixed lanes per light vertex (turns the autotuner off)")
+    p.add_argument("--no-autotune", action="store_true",
+                   help="keep the library's automatic settings instead of tuning them "
+                        "(untimed) on the workload first")
+    p.add_argument("--tune-budget", type=float, default=20.0)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 1 GiB device copy three times (scales the "
@@ -111,6 +116,13 @@ def main():
     out = torch.empty(g.n, dtype=torch.int32, device=dev)
 
     G = gc.Graph(rp, ci, mode=args.mode, algorithm=args.algorithm, lanes=args.lanes)
+    tuned = None
+    if not args.no_autotune and args.lanes == 0:
+        from paper_1509_08267_amd import autotune
+        res = autotune.tune(G, budget_s=args.tune_budget)
+        tuned = dict(res.setting, cached=res.cached, measurements=len(res.table),
+                     ms_start=None if res.cached else round(res.baseline_seconds * 1e3, 4),
+                     ms_best=round(res.seconds * 1e3, 4))
     t0 = time.perf_counter()
     G.color(out)
     rounds, ncolors = G.stats()
@@ -148,6 +160,9 @@ def main():
     sbytes = G.get(gc.GC_OPT_STATE_BYTES)
     algo = "push" if G.get(gc.GC_OPT_ALGORITHM) == gc.GC_ALGO_PUSH else "pull"
     lanes = G.get(gc.GC_OPT_LANES)
+    G_medium = G.get(gc.GC_OPT_MEDIUM_DEGREE)
+    G_heavy = G.get(gc.GC_OPT_HEAVY_DEGREE)
+    G_bpc = G.get(gc.GC_OPT_BLOCKS_PER_CU)
     G.close()
 
     t_step = elapsed / args.steps
@@ -216,7 +231,23 @@ def main():
                                            / ((spec_ms if kernel == "detect" else det_ms) / 1e3)
                                            / 1e9, 1) if min(spec_ms, det_ms) > 0 else None},
     }
+    if traffic:
+        # bytes the counters saw per launch over the measured launch time
+        roofline["traffic_gbs"] = round(traffic / (k_ms / 1e3 / max(1, k_launches)) / 1e9, 1)
+        roofline["traffic_frac"] = round(roofline["traffic_gbs"] / HBM_PEAK_GBS, 4)
     kernels_ms_per_step = {k: round(v[0] / max(1, calls), 4) for k, v in prof.items()}
+    # The whole colouring priced with the pull-based per-unit byte figures
+    # (8 B per neighbour visit in speculate and per lower-neighbour visit in
+    # detect, plus per uncoloured vertex two rowptr pairs, worklist and state
+    # bytes), i.e. what a pull implementation of the same rounds must move,
+    # over the timed step.
+    pull_bytes = (8 * golden["sum_active_deg"] + 8 * golden["sum_active_lower_deg"]
+                  + golden["sum_active"] * (2 * (4 + 2 * rp_b + 4) + 4))
+    step_roofline = {"definition": "pull-equivalent bytes per colouring",
+                     "bytes": pull_bytes,
+                     "achieved": round(pull_bytes / t_step / 1e9, 1), "unit": "GB/s",
+                     "peak": HBM_PEAK_GBS,
+                     "frac": round(pull_bytes / t_step / 1e9 / HBM_PEAK_GBS, 4)}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -248,7 +279,9 @@ def main():
         "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": g.n, "m": g.m, "nnz": g.nnz, "seed": 0,
-                   "mode": args.mode, "algorithm": algo, "lanes": lanes, "state_bytes": sbytes},
+                   "mode": args.mode, "algorithm": algo, "lanes": lanes, "state_bytes": sbytes,
+                   "medium_degree": G_medium, "heavy_degree": G_heavy,
+                   "blocks_per_cu": G_bpc, "autotuned": tuned},
         "vertices_per_s": round(g.n / t_step, 1),
         "colors": ncolors,
         "colors_seq": golden.get("seq_num_colors"),
@@ -258,6 +291,7 @@ def main():
         "profiled_ms_per_step": round(elapsed_prof / args.steps * 1e3, 4),
         "kernel_ms_per_step": kernels_ms_per_step,
         "roofline": roofline,
+        "step_roofline_pull_equivalent": step_roofline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)
