@@ -34,7 +34,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--workload", default="er_1m_16m")
     p.add_argument("--mode", default="graph")
-    p.add_argument("--algorithm", default="auto", choices=["auto", "pull", "push"])
+    p.add_argument("--algorithm", default="auto", choices=["auto", "pull", "push", "seq"],
+                   help="seq: the sequential First-Fit colouring computed in rounds")
     p.add_argument("--lanes", type=int, default=0,
                    help="fixed lanes per light vertex (turns the autotuner off)")
     p.add_argument("--no-autotune", action="store_true",
@@ -131,7 +132,10 @@ def main():
         G.color(out)
     G.stats()
     got = hashlib.sha256(out.cpu().numpy().astype(np.int32).tobytes()).hexdigest()
-    parity = got == golden["colors_sha256"] and rounds == golden["rounds"]
+    if args.algorithm == "seq":
+        parity = got == golden["seq_colors_sha256"] and rounds == golden["seq_rounds"]
+    else:
+        parity = got == golden["colors_sha256"] and rounds == golden["rounds"]
 
     # timed region 1: the library's default path, K back-to-back colourings
     torch.cuda.synchronize()
@@ -158,7 +162,8 @@ def main():
     prof = G.profile()
     G.set("profile", 0)
     sbytes = G.get(gc.GC_OPT_STATE_BYTES)
-    algo = "push" if G.get(gc.GC_OPT_ALGORITHM) == gc.GC_ALGO_PUSH else "pull"
+    algo = {gc.GC_ALGO_PUSH: "push", gc.GC_ALGO_PULL: "pull",
+            gc.GC_ALGO_SEQ: "seq"}[G.get(gc.GC_OPT_ALGORITHM)]
     lanes = G.get(gc.GC_OPT_LANES)
     G_medium = G.get(gc.GC_OPT_MEDIUM_DEGREE)
     G_heavy = G.get(gc.GC_OPT_HEAVY_DEGREE)
@@ -207,6 +212,18 @@ def main():
     if algo == "push":
         det_bytes += push_rows * (4 + sbytes) \
             + golden["push_useful_after_round1"]
+    if algo == "seq":
+        # pick (speculate kernel), rounds 2..R: per visit the rowptr pair and
+        # the vertex's state; per waiting visit at least one lower-neighbour
+        # entry and its state; per vertex coloured, its row once (entry +
+        # state gather) and the state write.  Commit (detect kernel): per
+        # visit a state read, per vertex coloured a state write.
+        sv = golden["seq_visits_after_round1"]
+        sc = golden["seq_coloured_after_round1"]
+        spec_bytes = (sv * (2 * rp_b + sbytes) + golden["seq_waiting_visits_after_round1"]
+                      * (4 + sbytes) + golden["seq_rows_after_round1"] * (4 + sbytes)
+                      + sc * sbytes)
+        det_bytes = sv * sbytes + sc * sbytes
     spec_ms, spec_launches = prof["speculate"]
     det_ms, det_launches = prof["detect"]
     kernel = "detect" if det_ms > spec_ms else "speculate"
@@ -243,7 +260,7 @@ def main():
     # over the timed step.
     pull_bytes = (8 * golden["sum_active_deg"] + 8 * golden["sum_active_lower_deg"]
                   + golden["sum_active"] * (2 * (4 + 2 * rp_b + 4) + 4))
-    step_roofline = {"definition": "pull-equivalent bytes per colouring",
+    step_roofline = None if algo == "seq" else {"definition": "pull-equivalent bytes per colouring",
                      "bytes": pull_bytes,
                      "achieved": round(pull_bytes / t_step / 1e9, 1), "unit": "GB/s",
                      "peak": HBM_PEAK_GBS,
@@ -257,11 +274,12 @@ def main():
         tstart = time.perf_counter()
         while len(ts) < 3 and (time.perf_counter() - tstart) < budget:
             t = time.perf_counter()
-            oracle.rsc(g.rowptr, g.colidx)
+            (oracle.seq if algo == "seq" else oracle.rsc)(g.rowptr, g.colidx)
             ts.append(time.perf_counter() - t)
         tb = min(ts)
         cpu = {"value": round(g.m / tb / 1e9, 5), "unit": "GTEPS", "cores": 1, "kind": "oracle",
-               "sample": f"whole {args.workload} graph, best of {len(ts)} single-thread runs "
+               "sample": f"whole {args.workload} graph, oracle "
+                         f"{'seq' if algo == 'seq' else 'rsc'}, best of {len(ts)} single-thread runs "
                          f"({tb:.2f} s each)",
                "seconds": round(tb, 3)}
 
@@ -285,6 +303,7 @@ def main():
         "vertices_per_s": round(g.n / t_step, 1),
         "colors": ncolors,
         "colors_seq": golden.get("seq_num_colors"),
+        "rounds_seq": golden.get("seq_rounds"),
         "rounds": rounds,
         "parity_vs_oracle": parity,
         "first_call_ms": round(t_first * 1e3, 3),

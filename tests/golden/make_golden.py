@@ -4,6 +4,7 @@ Every value in the output comes from ``graphgen`` (the inputs) and ``oracle``
 (the answers) only.  Run from the repository root:
 
     python tests/golden/make_golden.py [workload ...]
+    python tests/golden/make_golden.py --seq-only [workload ...]
 
 Per workload it records the input's SHA-256 and shape, the oracle's round
 count, colour count and the SHA-256 of its colour vector, the per-round
@@ -136,10 +137,31 @@ def one(name):
     rec.update(skip_fields(g, r))
     assert oracle.check_proper(g.rowptr, g.colidx, r.colors) == 0
     assert oracle.check_grundy(g.rowptr, g.colidx, r.colors) == 0
+    rec.update(seq_fields(g))
+    return rec
+
+
+def seq_fields(g):
+    """Sequential First Fit (the Section 5 baseline) and the rounds of the
+    id-priority schedule that reproduces it."""
     t = time.perf_counter()
     s = oracle.seq(g.rowptr, g.colidx)
-    rec["seq_seconds"] = time.perf_counter() - t
-    rec["seq_num_colors"] = int(s.max()) + 1 if s.size else 0
+    rec = {"seq_seconds": time.perf_counter() - t,
+           "seq_num_colors": int(s.max()) + 1 if s.size else 0,
+           "seq_colors_sha256": colors_sha(s)}
+    R, ro = oracle.seq_rounds(g.rowptr, g.colidx)
+    ro = ro.astype(np.int64)
+    deg = np.diff(g.rowptr).astype(np.int64)
+    rec["seq_rounds"] = R
+    # a vertex is uncoloured in rounds 1 .. round_of(v): sum of |U_r|
+    rec["seq_sum_active"] = int(ro.sum())
+    # the same counts restricted to rounds >= 2 (round 1 has its own launch):
+    # visits, visits of vertices still waiting, and the rows of the vertices
+    # coloured then (each read once for the least absent colour)
+    rec["seq_visits_after_round1"] = int(np.maximum(ro - 1, 0).sum())
+    rec["seq_waiting_visits_after_round1"] = int(np.maximum(ro - 2, 0).sum())
+    rec["seq_rows_after_round1"] = int(deg[ro >= 2].sum())
+    rec["seq_coloured_after_round1"] = int((ro >= 2).sum())
     return rec
 
 
@@ -148,6 +170,16 @@ def main(names):
     if os.path.exists(OUT):
         with open(OUT) as f:
             data = json.load(f)
+    if names and names[0] == "--seq-only":
+        # refresh only the sequential-baseline fields of recorded workloads
+        for name in names[1:] or [k for k in data if k != "er_batch_4096"]:
+            g = graphgen.workload(name)
+            assert g.sha256() == data[name]["input_sha256"]
+            data[name].update(seq_fields(g))
+            print(f"[golden] {name}: seq rounds {data[name]['seq_rounds']}", flush=True)
+        with open(OUT, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+        return
     for name in names:
         print(f"[golden] {name} ...", flush=True)
         data[name] = one(name)
