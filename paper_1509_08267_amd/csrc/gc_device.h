@@ -258,8 +258,9 @@ __device__ __forceinline__ bool detect_lane_skip(const int32_t* __restrict__ col
 // none) with colour t.  The segments are concatenated in lane order; entry j
 // of the concatenation belongs to the last lane whose exclusive prefix is
 // <= j, found by binary search over the prefixes with cross-lane reads.
-// Each lane keeps four entries in flight.  Stores as in push_colour.
-template <typename RP, typename S>
+// Each lane keeps four entries in flight.  Stores as in push_colour; without
+// CHECK_STATE every entry is taken to be still uncoloured (the caller knows).
+template <typename RP, typename S, bool CHECK_STATE = true>
 __device__ __forceinline__ void push_flat(const KArgs& a, const S* __restrict__ st, RP pb, int len,
                                           int t, int epoch) {
   const int lane = lane_id();
@@ -293,7 +294,7 @@ __device__ __forceinline__ void push_flat(const KArgs& a, const S* __restrict__ 
     }
     int s[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) s[q] = ok[q] ? (int)st[u[q]] : 0;
+    for (int q = 0; q < 4; ++q) s[q] = ok[q] && CHECK_STATE ? (int)st[u[q]] : -1;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       if (!ok[q] || s[q] >= 0) continue;

@@ -240,9 +240,10 @@ __device__ void light_phase(const KArgs& a, long wave_gid, long nwaves, Tally& t
       RP pb = 0;
       int len = 0;
       if (act) {
-        int sk = a.skip[v];
+        const int sk0 = a.skip[v];
+        int sk = sk0;
         const bool lose = detect_lane_skip<RP, S>(a.colidx, st, b, e, v, t, &sk);
-        a.skip[v] = sk;
+        if (sk != sk0) a.skip[v] = sk;
         if (!lose) {
           st[v] = (S)t;
           pb = b + sk;
@@ -520,6 +521,44 @@ __global__ __launch_bounds__(kBlock) void k_round1_sorted(KArgs a) {
   publish_detect(a, 1, tl, sm);
 }
 
+// Round 1 in closed form with pushes (sorted rows, push algorithm, no heavy
+// vertices): as
+// k_round1_sorted, and each winner marks colour 0 taken for all of its
+// neighbours, every one of which has a lower neighbour (the winner) and so
+// loses round 1.  Chunks of 64 vertices per wave; the winners of a chunk
+// push together.
+template <typename RP, typename S>
+__global__ __launch_bounds__(kBlock) void k_round1_sorted_push(KArgs a) {
+  __shared__ HeavySmem sm;
+  const RP* __restrict__ rp = (const RP*)a.rowptr;
+  S* __restrict__ st = (S*)a.st;
+  const int epoch = a.ctrl->epoch.v;
+  Tally tl{0, 0};
+  const long wave_gid = blockIdx.x * (long)kWavesPerBlock + threadIdx.x / kWave;
+  const long nwaves = (long)gridDim.x * kWavesPerBlock;
+  const long nchunks = ((long)a.n + kWave - 1) / kWave;
+  for (long ch = wave_gid; ch < nchunks; ch += nwaves) {
+    const int v = (int)(ch * kWave) + lane_id();
+    RP pb = 0;
+    int len = 0;
+    if (v < a.n) {
+      const RP b = rp[v], e = rp[v + 1];
+      const bool lose = e > b && a.colidx[b] < v;
+      st[v] = lose ? (S)-1 : (S)0;
+      a.skip[v] = 0;
+      tl.lost += lose;
+      tl.active += 1;
+      if (!lose) {
+        pb = b;
+        len = (int)(e - b);
+      }
+    }
+    push_flat<RP, S, false>(a, st, pb, len, 0, epoch);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.ctrl->more[0].v = 0;  // (1 + 2) % 3
+  publish_detect(a, 1, tl, sm);
+}
+
 // Unsorted rows: initialise every vertex to "tentative 0"; the general
 // detect phase then runs round 1.
 template <typename S>
@@ -764,6 +803,12 @@ template <typename RP, typename S, int L>
 static int launch_round1_t(const KArgs& a, int grid, hipStream_t s) {
   if (a.sorted && !a.push && !a.seq) {
     hipLaunchKernelGGL((k_round1_sorted<RP, S>), dim3(grid), dim3(kBlock), 0, s, a);
+    return (int)hipGetLastError();
+  }
+  // (a heavy winner would push its whole row from one wavefront: those
+  // graphs take the general round-1 pass, whose heavy path uses a workgroup)
+  if (a.sorted && a.push && a.hcount == 0) {
+    hipLaunchKernelGGL((k_round1_sorted_push<RP, S>), dim3(grid), dim3(kBlock), 0, s, a);
     return (int)hipGetLastError();
   }
   hipLaunchKernelGGL((k_fill_tent0<S>), dim3(grid), dim3(kBlock), 0, s, a);
