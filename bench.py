@@ -42,6 +42,9 @@ def parse():
                    help="keep the library's automatic settings instead of tuning them "
                         "(untimed) on the workload first")
     p.add_argument("--tune-budget", type=float, default=20.0)
+    p.add_argument("--batch-only", action="store_true",
+                   help="batched workload: time the one-launch batch only (no per-graph "
+                        "or served comparison); for profiling runs")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 1 GiB device copy three times (scales the "
@@ -64,7 +67,7 @@ def kernel_source_hash():
     """Hash of the kernel sources and of the engine that picks their launch
     shape; a committed counter summary is used only while it matches."""
     h = hashlib.sha256()
-    for f in ("gc_kernels.hip", "gc_internal.h", "gc_api.hip"):
+    for f in ("gc_kernels.hip", "gc_batch.hip", "gc_device.h", "gc_internal.h", "gc_api.hip"):
         with open(os.path.join(ROOT, "paper_1509_08267_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -369,6 +372,12 @@ def run_batch(args, golden):
     kernel_ms = start.elapsed_time(end) / steps
     t_step = elapsed / steps
 
+    t_pergraph = None
+    served = None
+    if args.batch_only:
+        return batch_record(args, golden, b, G, m, n, t_step, kernel_ms, steps, parity,
+                            t_pergraph, served)
+
     # per-graph path on the same graphs (handles made untimed, rounds known)
     handles = []
     for gi in range(G):
@@ -417,6 +426,11 @@ def run_batch(args, golden):
         rec = {"load": frac, "rate_per_s": round(lam, 1), "achieved_per_s": round(G / dt, 1)}
         rec.update({k: round(v, 3) for k, v in serve.latency_summary(jobs).items()})
         served["poisson"].append(rec)
+    return batch_record(args, golden, b, G, m, n, t_step, kernel_ms, steps, parity,
+                        t_pergraph, served)
+
+
+def batch_record(args, golden, b, G, m, n, t_step, kernel_ms, steps, parity, t_pergraph, served):
 
     # HBM roofline of the batch kernel: colidx entries the rounds read
     # (speculate: every neighbour of every uncoloured vertex of rounds >= 2;
@@ -426,6 +440,15 @@ def run_batch(args, golden):
     alg = 4 * (golden["sum_active_deg"] - int(b.eoff[-1]) + golden["sum_active_lower_deg"]) \
         + 8 * golden["sum_active"]
     achieved = alg / (kernel_ms / 1e3) / 1e9
+    traffic = measured_traffic(args.workload, "batch")
+    roofline = {"kernel": "gc_color_batch (k_batch_color)", "bound": "hbm",
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "alg_bytes_per_launch": alg, "avg_launch_us": round(kernel_ms * 1e3, 1),
+                "launches": steps}
+    if traffic:
+        roofline["traffic_gbs"] = round(traffic / (kernel_ms / 1e3) / 1e9, 1)
+        roofline["traffic_frac"] = round(roofline["traffic_gbs"] / HBM_PEAK_GBS, 4)
     rec = {
         "metric": METRIC,
         "value": round(m / t_step / 1e9, 3),
@@ -446,17 +469,34 @@ def run_batch(args, golden):
         "parity_vs_oracle": parity,
         "colors_max": golden["num_colors_max"],
         "rounds_max": golden["rounds_max"],
-        "per_graph_path": {"ms": round(t_pergraph * 1e3, 2), "GTEPS": round(m / t_pergraph / 1e9, 3),
-                           "graphs_per_s": round(G / t_pergraph, 1)},
-        "batch_gain_over_per_graph": round(t_pergraph / t_step, 2),
+        "per_graph_path": None if t_pergraph is None else {
+            "ms": round(t_pergraph * 1e3, 2), "GTEPS": round(m / t_pergraph / 1e9, 3),
+            "graphs_per_s": round(G / t_pergraph, 1)},
+        "batch_gain_over_per_graph": None if t_pergraph is None else round(t_pergraph / t_step, 2),
         "served": served,
-        "roofline": {"kernel": "k_batch_color", "bound": "hbm", "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "alg_bytes_per_launch": alg,
-                     "avg_launch_us": round(kernel_ms * 1e3, 1), "launches": steps},
-        "cpu_baseline": None,
+        "roofline": roofline,
+        "cpu_baseline": None if args.no_cpu_baseline else batch_cpu_baseline(b),
     }
     print(json.dumps(rec), flush=True)
+
+
+def batch_cpu_baseline(b, budget=15.0):
+    """The oracle on the batch's first graphs, one at a time in order, until
+    `budget` seconds of single-thread work; GTEPS over the graphs done."""
+    import oracle
+    t_total, edges, done = 0.0, 0, 0
+    while done < b.num_graphs and t_total < budget:
+        g = b.graph(done)
+        t = time.perf_counter()
+        oracle.rsc(g.rowptr, g.colidx)
+        t_total += time.perf_counter() - t
+        edges += g.nnz // 2
+        done += 1
+    return {"value": round(edges / t_total / 1e9, 5), "unit": "GTEPS", "cores": 1,
+            "kind": "oracle",
+            "sample": f"the first {done} of {b.num_graphs} graphs of the batch, each coloured by "
+                      f"the single-thread oracle ({t_total:.1f} s, {edges} edges)",
+            "seconds": round(t_total, 3)}
 
 
 if __name__ == "__main__":

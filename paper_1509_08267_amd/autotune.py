@@ -12,7 +12,7 @@ It picks, for one graph on one device:
 It times colourings of the graph itself and walks the knobs one at a time
 (coordinate descent: each knob is set to its fastest candidate with the others
 held, in the order above).  The choice is cached in a JSON file keyed by the
-device (name, architecture, compute units) and a graph class (id width, log2
+device (architecture, compute units, memory) and a graph class (id width, log2
 buckets of n, average and maximum degree, algorithm), so later graphs of the
 same class reuse it without timing.
 
@@ -64,9 +64,11 @@ def graph_class(n: int, nnz: int, max_degree: int, rowptr_i64: bool, algorithm: 
 
 
 def device_key(device: int = 0) -> str:
+    """Architecture, compute units and memory size (the marketing name is
+    left out: it is not reported the same way under every tool)."""
     p = torch.cuda.get_device_properties(device)
     arch = getattr(p, "gcnArchName", "")
-    return f"{p.name}|{arch}|cu{p.multi_processor_count}"
+    return f"{arch}|cu{p.multi_processor_count}|mem{p.total_memory >> 30}GiB"
 
 
 def coordinate_descent(knobs, candidates, measure, start):
