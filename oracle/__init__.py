@@ -56,6 +56,8 @@ def _load():
         lib.oracle_seq.argtypes = [i64, p, p, p]
         lib.oracle_seq_rounds.restype = i64
         lib.oracle_seq_rounds.argtypes = [i64, p, p, p]
+        lib.oracle_blocks.restype = i64
+        lib.oracle_blocks.argtypes = [i64, p, p, i64, p, p]
         lib.oracle_check_proper.restype = i64
         lib.oracle_check_proper.argtypes = [i64, p, p, p]
         lib.oracle_check_grundy.restype = i64
@@ -120,6 +122,19 @@ def seq_rounds(rowptr, colidx):
     if R < 0:
         raise ValueError("oracle_seq_rounds rejected its input")
     return int(R), rounds[:n]
+
+
+def blocks(rowptr, colidx, p: int):
+    """(colours, R, recolours) of Algorithm 1 with p blocks, read literally."""
+    rp, ci = _csr(rowptr, colidx)
+    n = rp.shape[0] - 1
+    colors = np.zeros(max(n, 1), np.int32)
+    rec = np.zeros(max(n, 1), np.int32)
+    R = _load().oracle_blocks(n, rp.ctypes.data, ci.ctypes.data, int(p), colors.ctypes.data,
+                              rec.ctypes.data)
+    if R < 0:
+        raise ValueError("oracle_blocks rejected its input")
+    return colors[:n], int(R), rec[:n]
 
 
 def check_proper(rowptr, colidx, colors) -> int:

@@ -43,6 +43,11 @@
  *                  every vertex that same colour: the longest id-increasing
  *                  path ending at each vertex.
  *
+ *   oracle_blocks -- Algorithm 1 with p blocks of consecutive ids, read
+ *                  literally (per-edge ForbiddenColors slots, sequential
+ *                  First Fit inside a block, the lower partition recoloured);
+ *                  its own readings are listed at the function.
+ *
  *   oracle_check_* -- what the problem statement (Section 2.1) and Lemma 1
  *                  (Section 4) fix: a proper colouring, and First-Fit's
  *                  Grundy property (each colour is the least one absent from
@@ -224,6 +229,102 @@ int64_t oracle_seq_rounds(int64_t n, const int64_t *rowptr, const int32_t *colid
     if (d + 1 > R) R = d + 1;
   }
   return R;
+}
+
+/*
+ * Algorithm 1 of Section 3.1 read literally, with p blocks (the p-block
+ * variant).  Readings taken where the paper is loose:
+ *   - block(v) = floor(v * p / n): p blocks of consecutive ids, sizes
+ *     differing by at most one (the paper's uniform partition with ids from 0);
+ *   - every vertex keeps one ForbiddenColors slot per CSR entry, initialised
+ *     to -1;
+ *   - phase 1: each block takes its vertices still to colour in increasing id
+ *     order; v gets the least colour in 0..(max degree) absent from its slots,
+ *     then writes that colour into the slot for v of each neighbour in the
+ *     same block (so a block colours sequentially, seeing its own colours at
+ *     once);
+ *   - phase 2: each vertex v still to colour that has a neighbour in another
+ *     block refreshes its slot for every such neighbour u with u's colour
+ *     after this round's phase 1, and is recoloured (the set to recolour
+ *     collects v itself) when some such u has v's colour and lies in a
+ *     higher-numbered block (the paper's "vertex in the lower partition is
+ *     recoloured"); a slot for a foreign neighbour is therefore only as fresh
+ *     as v's last phase 2 (stale colours stay visible);
+ *   - rounds continue until no block has a vertex to recolour; R counts the
+ *     phase-1 passes.
+ * color_out[n] receives the colours, recolours_out[n] (may be NULL) the
+ * number of rounds after the first in which each vertex was coloured again.
+ * Returns R (0 when n == 0), or -1 on bad arguments or allocation failure.
+ */
+int64_t oracle_blocks(int64_t n, const int64_t *rowptr, const int32_t *colidx, int64_t p,
+                      int32_t *color_out, int32_t *recolours_out) {
+  if (n < 0 || p < 1 || (n > 0 && (!rowptr || !color_out))) return -1;
+  if (n == 0) return 0;
+  int64_t maxdeg = 0;
+  for (int64_t v = 0; v < n; ++v) {
+    int64_t d = rowptr[v + 1] - rowptr[v];
+    if (d > maxdeg) maxdeg = d;
+  }
+  const int64_t nnz = rowptr[n];
+  int32_t *slot = (int32_t *)malloc(((size_t)nnz + 1) * sizeof(int32_t));
+  int64_t *blk = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+  unsigned char *todo = (unsigned char *)malloc((size_t)n);
+  unsigned char *lose = (unsigned char *)malloc((size_t)n);
+  unsigned char *used = (unsigned char *)calloc((size_t)maxdeg + 2, 1);
+  if (!slot || !blk || !todo || !lose || !used) {
+    free(slot); free(blk); free(todo); free(lose); free(used);
+    return -1;
+  }
+  for (int64_t k = 0; k < nnz; ++k) slot[k] = -1;
+  for (int64_t v = 0; v < n; ++v) {
+    blk[v] = (int64_t)(((__int128)v * p) / n);
+    todo[v] = 1;
+    color_out[v] = -1;
+    if (recolours_out) recolours_out[v] = 0;
+  }
+  int64_t rounds = 0, left = n;
+  while (left > 0) {
+    ++rounds;
+    /* phase 1: blocks are independent (only same-block slots are written);
+     * within a block, increasing id order */
+    for (int64_t v = 0; v < n; ++v) {
+      if (!todo[v]) continue;
+      for (int64_t k = rowptr[v]; k < rowptr[v + 1]; ++k)
+        if (slot[k] >= 0 && slot[k] <= maxdeg) used[slot[k]] = 1;
+      int32_t c = 0;
+      while (used[c]) ++c;
+      for (int64_t k = rowptr[v]; k < rowptr[v + 1]; ++k)
+        if (slot[k] >= 0 && slot[k] <= maxdeg) used[slot[k]] = 0;
+      if (color_out[v] >= 0 && recolours_out) ++recolours_out[v];
+      color_out[v] = c;
+      /* the slot for v in each same-block neighbour's list */
+      for (int64_t k = rowptr[v]; k < rowptr[v + 1]; ++k) {
+        int64_t u = colidx[k];
+        if (blk[u] != blk[v]) continue;
+        for (int64_t q = rowptr[u]; q < rowptr[u + 1]; ++q)
+          if (colidx[q] == v) slot[q] = c;
+      }
+    }
+    /* (barrier) phase 2 */
+    for (int64_t v = 0; v < n; ++v) {
+      lose[v] = 0;
+      if (!todo[v]) continue;
+      for (int64_t k = rowptr[v]; k < rowptr[v + 1]; ++k) {
+        int64_t u = colidx[k];
+        if (blk[u] == blk[v]) continue;
+        slot[k] = color_out[u];
+        if (color_out[u] == color_out[v] && blk[v] < blk[u]) lose[v] = 1;
+      }
+    }
+    left = 0;
+    for (int64_t v = 0; v < n; ++v) {
+      todo[v] = lose[v];
+      left += lose[v];
+    }
+    /* (barrier) */
+  }
+  free(slot); free(blk); free(todo); free(lose); free(used);
+  return rounds;
 }
 
 /* Number of CSR entries (v, u) with color[v] == color[u], plus the number of

@@ -12,6 +12,8 @@ passages, so that a slip in one is caught by the other:
 * ``seq_schedule`` -- the same colours by rounds: a vertex is coloured once
   its lower neighbours are; ``longest_increasing_path`` gives its round by
   enumeration.
+* ``blocks`` -- Algorithm 1 read literally with p blocks of consecutive ids
+  (per-edge forbidden slots, the lower-numbered block recoloured).
 * ``chromatic_number`` -- brute force over all colourings, for n <= 10,
   the quantity the paper's objective minimises (Section 2.1).
 
@@ -111,6 +113,42 @@ def seq_schedule(adj):
             round_of[v] = r
         waiting -= set(ready)
     return col, r, round_of
+
+
+def blocks(adj, p):
+    """Algorithm 1 with p blocks, from the pseudo-code: per-edge forbidden
+    slots, phase 1 sequential inside each block (increasing id), phase 2
+    refreshing the slots of foreign neighbours and recolouring the vertex of
+    the lower-numbered block.  Returns (colours, rounds, recolours)."""
+    n = len(adj)
+    if n == 0:
+        return [], 0, []
+    block = [v * p // n for v in range(n)]
+    forbidden = {v: {u: -1 for u in adj[v]} for v in range(n)}
+    colour = [-1] * n
+    recol = [0] * n
+    todo = set(range(n))
+    rounds = 0
+    while todo:
+        rounds += 1
+        for b in sorted(set(block[v] for v in todo)):
+            for v in sorted(x for x in todo if block[x] == b):
+                c = mex(forbidden[v].values())
+                if colour[v] >= 0:
+                    recol[v] += 1
+                colour[v] = c
+                for u in adj[v]:
+                    if block[u] == b:
+                        forbidden[u][v] = c
+        again = set()
+        for v in todo:
+            for u in adj[v]:
+                if block[u] != block[v]:
+                    forbidden[v][u] = colour[u]
+                    if colour[u] == colour[v] and block[v] < block[u]:
+                        again.add(v)
+        todo = again
+    return colour, rounds, recol
 
 
 def is_proper(adj, col) -> bool:

@@ -197,6 +197,82 @@ def test_seq_rounds_pins_reject_a_reversed_dependency():
     assert wrong(g) != list(oracle.seq_rounds(*_csr(g))[1])
 
 
+# ------------------------------- Algorithm 1 with p blocks, read literally --
+
+def test_blocks_hand_worked_path():
+    # path 0-1-2, p = 3: round 1 all take 0; 0 and 1 lose to their higher
+    # neighbours; round 2 both take 1 (their slots hold 0), 0 loses to 1
+    # again; round 3 vertex 0 sees 1 in its slot and takes 0
+    col, R, rec = oracle.blocks(*_csr(graphgen.path(3)), 3)
+    assert list(col) == [0, 1, 0] and R == 3 and list(rec) == [2, 1, 0]
+
+
+def test_blocks_star_centre_in_lowest_block():
+    # every vertex its own block: the centre (block 0) loses to every leaf
+    # in round 1 and takes 1 in round 2
+    col, R, rec = oracle.blocks(*_csr(graphgen.star(6, centre=0)), 7)
+    assert list(col) == [1] + [0] * 6 and R == 2 and list(rec) == [1] + [0] * 6
+
+
+def test_blocks_one_block_is_sequential_first_fit():
+    for g in list(_random_graphs(300, 12, seed=31)) + [graphgen.er(2000, 16000, 2)]:
+        col, R, rec = oracle.blocks(g.rowptr, g.colidx, 1)
+        assert list(col) == list(oracle.seq(g.rowptr, g.colidx))
+        assert R == (1 if g.n else 0) and not rec.any()
+
+
+def test_blocks_lemma_bounds_and_properness():
+    # Lemma 1: proper.  Lemma 2's argument: block V_p never loses, and each
+    # lower block settles one round after the block above it, so R <= p and a
+    # vertex of block b (0-based) is coloured again at most p - 1 - b times
+    for g in list(_random_graphs(300, 14, seed=32)) + [graphgen.er(3000, 30000, 3)]:
+        for p in (1, 2, 3, 5, 8, max(1, g.n)):
+            col, R, rec = oracle.blocks(g.rowptr, g.colidx, p)
+            if g.n == 0:
+                continue
+            assert oracle.check_proper(g.rowptr, g.colidx, col) == 0
+            assert R <= p
+            blk = np.arange(g.n) * p // g.n
+            assert np.all(rec <= p - 1 - blk)
+            assert np.all(col <= np.diff(g.rowptr))
+
+
+def test_blocks_c_matches_python():
+    for g in _random_graphs(1500, 11, seed=33):
+        for p in (1, 2, 3, 4, 7, max(1, g.n)):
+            col, R, rec = oracle.blocks(g.rowptr, g.colidx, p)
+            c2, R2, rec2 = ref_py.blocks(adj(g), p)
+            assert list(col) == c2 and R == R2 and list(rec) == rec2
+
+
+def test_blocks_pins_reject_higher_partition_losing():
+    # the opposite tie-break (the higher block recoloured) breaks the star pin
+    def flipped(a, p):
+        n = len(a)
+        block = [v * p // n for v in range(n)]
+        fb = {v: {u: -1 for u in a[v]} for v in range(n)}
+        col = [-1] * n
+        todo, R = set(range(n)), 0
+        while todo:
+            R += 1
+            for v in sorted(todo):
+                col[v] = ref_py.mex(fb[v].values())
+                for u in a[v]:
+                    if block[u] == block[v]:
+                        fb[u][v] = col[v]
+            again = set()
+            for v in todo:
+                for u in a[v]:
+                    if block[u] != block[v]:
+                        fb[v][u] = col[u]
+                        if col[u] == col[v] and block[v] > block[u]:
+                            again.add(v)
+            todo = again
+        return col, R
+    g = graphgen.star(6, centre=0)
+    assert flipped(adj(g), 7) != ([1] + [0] * 6, 2)
+
+
 # ------------------------------------------------------ properties (random) --
 
 def _random_graphs(count, nmax, seed):
