@@ -166,7 +166,8 @@ enum gc_option {
                                 the rounds are launched directly (not as a
                                 captured graph) with an event around every
                                 kernel; read with gc_get_profile           */
-  GC_OPT_ALGORITHM = 14      /* enum gc_algorithm (default GC_ALGO_AUTO)           */
+  GC_OPT_ALGORITHM = 14,     /* enum gc_algorithm (default GC_ALGO_AUTO)           */
+  GC_OPT_PARTITIONS = 15     /* p for GC_ALGO_BLOCKS; 0 = auto (64 per compute unit) */
 };
 /* The colouring to compute.  AUTO, PULL and PUSH compute the same colouring
  * (round-synchronous speculation, Algorithm 1 of Section 3.1 with every vertex
@@ -183,12 +184,22 @@ enum gc_algorithm {
                         no atomics); speculation reads its 32 flags and scans its
                         row only when colours 0..31 are all taken.  32 bytes per
                         vertex of device memory                                 */
-  GC_ALGO_SEQ = 3    /* sequential First Fit in id order, computed in rounds: a
+  GC_ALGO_SEQ = 3,   /* sequential First Fit in id order, computed in rounds: a
                         vertex takes the least colour absent from its lower-id
                         neighbours in the first round in which all of them are
                         coloured.  The colours equal the sequential ones bit for
                         bit; R is the number of vertices on the longest path
                         whose ids increase                                      */
+  GC_ALGO_BLOCKS = 4 /* Algorithm 1 of Section 3.1 read literally with p =
+                        GC_OPT_PARTITIONS blocks of consecutive ids: every
+                        vertex keeps a ForbiddenColors slot per neighbour; in
+                        each round a block colours its pending vertices
+                        sequentially (First Fit, increasing id), then each such
+                        vertex refreshes its slots for neighbours in other
+                        blocks and is recoloured if one in a higher block has
+                        its colour.  The colouring depends on p by design;
+                        R <= p.  4 bytes per CSR entry of device memory; the
+                        rounds are driven from the host                       */
 };
 enum gc_mode {
   GC_MODE_AUTO = 0,       /* currently GRAPH                                      */

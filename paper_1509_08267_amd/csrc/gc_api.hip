@@ -103,6 +103,9 @@ struct gc_ctx {
   bool in_flight = false;
   bool stats_ready = false;
   int64_t known_rounds = 0;  // R of this graph once a call has completed (0 = unknown)
+  int64_t partitions = 0;    // p of GC_ALGO_BLOCKS (0 = auto)
+  int32_t* bslot = nullptr;  // device, nnz: ForbiddenColors slots (GC_ALGO_BLOCKS)
+  uint8_t* btodo = nullptr;  // device, n
 
   Captured chunk;  // discovery chunk (chunk_rounds)
   Captured exact;  // R - 1 rounds, once R is known
@@ -172,6 +175,17 @@ static bool use_push(const gc_ctx* h) {
 }
 
 static bool use_seq(const gc_ctx* h) { return h->algorithm == GC_ALGO_SEQ; }
+
+// The colouring a handle computes: the speculative one (AUTO, PULL, PUSH),
+// sequential First Fit (SEQ), or Algorithm 1 with p blocks.  R is a property
+// of the graph and of this.
+static int family_of(int algorithm) {
+  return algorithm == GC_ALGO_SEQ ? 1 : algorithm == GC_ALGO_BLOCKS ? 2 : 0;
+}
+
+static int64_t partitions_of(const gc_ctx* h) {
+  return h->partitions > 0 ? h->partitions : (int64_t)h->cus * 64;
+}
 
 static KArgs make_args(const gc_ctx* h, int32_t* colors, int light_max) {
   KArgs a{};
@@ -243,6 +257,8 @@ static void free_ctx(gc_ctx* h) {
   if (h->wide) (void)hipFree(h->wide);
   if (h->widx) (void)hipFree(h->widx);
   if (h->skip) (void)hipFree(h->skip);
+  if (h->bslot) (void)hipFree(h->bslot);
+  if (h->btodo) (void)hipFree(h->btodo);
   if (h->host) (void)hipHostFree(h->host);
   delete h;
 }
@@ -445,6 +461,62 @@ static void collect_profile(gc_ctx* h) {
   h->timed_rounds = 0;
 }
 
+// Algorithm 1 with p blocks (GC_ALGO_BLOCKS): per-edge slots, p sequential
+// blocks per round; the host reads the count of vertices to recolour after
+// each round (R <= p).
+static int color_blocks(gc_ctx* h, int32_t* colors_out, hipStream_t s) {
+  int rc = GC_OK;
+  if (h->n > 0 && !h->bslot) {
+    hipError_t e = hipMalloc((void**)&h->bslot, (size_t)std::max<int64_t>(h->m, 1) * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc((void**)&h->btodo, (size_t)h->n);
+    if (e != hipSuccess) return set_err(h, GC_ENOMEM, "block slots: %s", hipGetErrorString(e));
+  }
+  h->stats_ready = false;
+  KArgs a = make_args(h, colors_out, light_max_of(h, auto_lanes(h)));
+  a.st = colors_out;  // the colours are the state (int32)
+  gc::BArgs b{};
+  b.rowptr = h->rowptr;
+  b.colidx = h->colidx;
+  b.color = colors_out;
+  b.slot = h->bslot;
+  b.todo = h->btodo;
+  b.n = (int32_t)h->n;
+  b.p = partitions_of(h);
+  b.ctrl = h->ctrl;
+  const int grid = grid_of(h);
+  LCHECK(h, gc::launch_init(a, s));
+  if (h->profile) HIPCHECK(h, hipEventRecord(h->pev[0], s));
+  if (h->n > 0) {
+    LCHECK(h, gc::launch_blocks_init(b, h->rp64, grid, s));
+    if (h->profile) HIPCHECK(h, hipEventRecord(h->pev[1], s));
+    for (int r = 1;; ++r) {
+      b.round = r;
+      LCHECK(h, gc::launch_blocks_round(b, h->rp64, grid, s));
+      HIPCHECK(h, hipMemcpyAsync(&h->host->flag, &h->ctrl->left.v, sizeof(int32_t),
+                                 hipMemcpyDeviceToHost, s));
+      HIPCHECK(h, hipStreamSynchronize(s));
+      if (!h->host->flag) break;
+      if (h->max_rounds > 0 && r >= h->max_rounds) break;
+    }
+  } else if (h->profile) {
+    HIPCHECK(h, hipEventRecord(h->pev[1], s));
+  }
+  if (h->profile) HIPCHECK(h, hipEventRecord(h->pev[2], s));
+  LCHECK(h, gc::launch_finish(a, 4, std::min(grid, 1024), s));
+  // a round cap can stop the loop with coloured vertices still in conflict
+  if (h->n > 0 && h->host->flag) LCHECK(h, gc::launch_blocks_set_left(h->ctrl, h->host->flag, s));
+  if (h->profile) HIPCHECK(h, hipEventRecord(h->pev[3], s));
+  h->pending_profile = h->profile;
+  HIPCHECK(h, hipMemcpyAsync(&h->host->last_round, &h->ctrl->last_round.v, 4, hipMemcpyDeviceToHost, s));
+  HIPCHECK(h, hipMemcpyAsync(&h->host->ncolors, &h->ctrl->ncolors.v, 4, hipMemcpyDeviceToHost, s));
+  HIPCHECK(h, hipMemcpyAsync(&h->host->abort, &h->ctrl->abort.v, 4, hipMemcpyDeviceToHost, s));
+  HIPCHECK(h, hipMemcpyAsync(&h->host->left, &h->ctrl->left.v, 4, hipMemcpyDeviceToHost, s));
+  HIPCHECK(h, hipEventRecord(h->done, s));
+  h->in_flight = true;
+  h->stats_ready = true;
+  return rc;
+}
+
 extern "C" int gc_color(gc_handle h, int32_t* colors_out, void* stream) {
   if (!h) return set_err(nullptr, GC_EINVAL, "gc_color: NULL handle");
   if (h->n > 0 && !colors_out) return set_err(h, GC_EINVAL, "gc_color: colors_out is NULL");
@@ -469,6 +541,7 @@ extern "C" int gc_color(gc_handle h, int32_t* colors_out, void* stream) {
     if (rc) return rc;
   }
   (void)hipGetLastError();  // launch checks below must see only this call's errors
+  if (h->algorithm == GC_ALGO_BLOCKS) return color_blocks(h, colors_out, s);
   if (use_push(h)) {
     if (!h->seen && h->n > 0) {
       hipError_t e = hipMalloc((void**)&h->seen, (size_t)h->n * gc::kPushColors);
@@ -674,12 +747,16 @@ extern "C" int gc_set_option(gc_handle h, int option, int64_t value) {
       h->persist_per_cu = (int)value;
       return GC_OK;
     case GC_OPT_ALGORITHM:
-      if (value < GC_ALGO_AUTO || value > GC_ALGO_SEQ) break;
+      if (value < GC_ALGO_AUTO || value > GC_ALGO_BLOCKS) break;
       // the round count R is a property of the graph and of the colouring
-      // computed: switching between the speculative colouring and SEQ
-      // forgets it
-      if ((value == GC_ALGO_SEQ) != use_seq(h)) h->known_rounds = 0;
+      // computed: switching to another colouring forgets it
+      if (family_of((int)value) != family_of(h->algorithm)) h->known_rounds = 0;
       h->algorithm = (int)value;
+      return GC_OK;
+    case GC_OPT_PARTITIONS:
+      if (value < 0 || value > INT32_MAX) break;
+      if (h->algorithm == GC_ALGO_BLOCKS) h->known_rounds = 0;
+      h->partitions = value;
       return GC_OK;
     case GC_OPT_PROFILE:
       if (value < 0 || value > 1) break;
@@ -712,8 +789,12 @@ extern "C" int gc_get_option(gc_handle h, int option, int64_t* value) {
     case GC_OPT_STATE_BYTES: *value = h->sbytes; return GC_OK;
     case GC_OPT_PROFILE: *value = h->profile; return GC_OK;
     case GC_OPT_ALGORITHM:
-      *value = use_seq(h) ? GC_ALGO_SEQ : use_push(h) ? GC_ALGO_PUSH : GC_ALGO_PULL;
+      *value = h->algorithm == GC_ALGO_BLOCKS ? GC_ALGO_BLOCKS
+               : use_seq(h)                   ? GC_ALGO_SEQ
+               : use_push(h)                  ? GC_ALGO_PUSH
+                                              : GC_ALGO_PULL;
       return GC_OK;
+    case GC_OPT_PARTITIONS: *value = partitions_of(h); return GC_OK;
     default: return set_err(h, GC_EINVAL, "gc_get_option: unknown option %d", option);
   }
 }

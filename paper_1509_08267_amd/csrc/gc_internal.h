@@ -72,6 +72,27 @@ struct KArgs {
   Ctrl* ctrl;
 };
 
+// Arguments of the p-block kernels (GC_ALGO_BLOCKS, gc_blocks.hip).
+struct BArgs {
+  const void* rowptr;     // int32 or int64, n + 1
+  const int32_t* colidx;  // nnz
+  int32_t* color;         // n: current colours (-1 before a vertex's first), the caller's output
+  int32_t* slot;          // nnz: ForbiddenColors slot of each entry whose neighbour is in
+                          // another block (entries within a block are not used)
+  uint8_t* todo;          // n: 1 while the vertex is to be (re)coloured
+  int32_t n;
+  int64_t p;              // blocks
+  int32_t round;          // round being run (1-based), for the trace
+  Ctrl* ctrl;
+};
+
+int launch_blocks_init(const BArgs& a, bool rp64, int grid, void* stream);
+// Phase 1, barrier, phase 2 of one round; ctrl->left receives the vertices
+// to recolour, ctrl->trace / last_round the round's size.
+int launch_blocks_round(const BArgs& a, bool rp64, int grid, void* stream);
+// ctrl->left = value (vertices still to recolour when a round cap stops the loop)
+int launch_blocks_set_left(Ctrl* c, int value, void* stream);
+
 // Records `msg` as the calling thread's last error (gc_last_error(NULL)).
 void set_thread_error(const char* msg);
 

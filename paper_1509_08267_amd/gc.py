@@ -28,10 +28,10 @@ GC_ROWPTR_I64, GC_VALIDATE, GC_ROWS_SORTED = 1, 2, 4
 (GC_OPT_MODE, GC_OPT_LANES, GC_OPT_HEAVY_DEGREE, GC_OPT_BLOCKS_PER_CU, GC_OPT_MAX_ROUNDS,
  GC_OPT_CHUNK_ROUNDS, GC_OPT_MEDIUM_DEGREE, GC_OPT_MAX_DEGREE, GC_OPT_MEDIUM_COUNT,
  GC_OPT_HEAVY_COUNT, GC_OPT_PERSISTENT_BLOCKS_PER_CU, GC_OPT_STATE_BYTES,
- GC_OPT_PROFILE, GC_OPT_ALGORITHM) = range(1, 15)
-GC_ALGO_AUTO, GC_ALGO_PULL, GC_ALGO_PUSH, GC_ALGO_SEQ = range(4)
+ GC_OPT_PROFILE, GC_OPT_ALGORITHM, GC_OPT_PARTITIONS) = range(1, 16)
+GC_ALGO_AUTO, GC_ALGO_PULL, GC_ALGO_PUSH, GC_ALGO_SEQ, GC_ALGO_BLOCKS = range(5)
 ALGORITHMS = {"auto": GC_ALGO_AUTO, "pull": GC_ALGO_PULL, "push": GC_ALGO_PUSH,
-              "seq": GC_ALGO_SEQ}
+              "seq": GC_ALGO_SEQ, "blocks": GC_ALGO_BLOCKS}
 PROFILE_KINDS = ("round1", "speculate", "detect", "finish")
 # enum gc_mode
 GC_MODE_AUTO, GC_MODE_HOST, GC_MODE_CHUNKED, GC_MODE_PERSISTENT, GC_MODE_GRAPH = range(5)
@@ -233,7 +233,8 @@ class Graph:
              "blocks_per_cu": GC_OPT_BLOCKS_PER_CU, "max_rounds": GC_OPT_MAX_ROUNDS,
              "chunk_rounds": GC_OPT_CHUNK_ROUNDS, "medium_degree": GC_OPT_MEDIUM_DEGREE,
              "persistent_blocks_per_cu": GC_OPT_PERSISTENT_BLOCKS_PER_CU,
-             "profile": GC_OPT_PROFILE, "algorithm": GC_OPT_ALGORITHM}
+             "profile": GC_OPT_PROFILE, "algorithm": GC_OPT_ALGORITHM,
+             "partitions": GC_OPT_PARTITIONS}
 
     def set(self, name: str, value):
         if name == "mode" and isinstance(value, str):
