@@ -34,8 +34,11 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--workload", default="er_1m_16m")
     p.add_argument("--mode", default="graph")
-    p.add_argument("--algorithm", default="auto", choices=["auto", "pull", "push", "seq"],
-                   help="seq: the sequential First-Fit colouring computed in rounds")
+    p.add_argument("--algorithm", default="auto",
+                   choices=["auto", "pull", "push", "seq", "blocks"],
+                   help="seq: the sequential First-Fit colouring computed in rounds; "
+                        "blocks: Algorithm 1 read literally with the recorded number of "
+                        "blocks (p = 16384)")
     p.add_argument("--lanes", type=int, default=0,
                    help="fixed lanes per light vertex (turns the autotuner off)")
     p.add_argument("--no-autotune", action="store_true",
@@ -119,9 +122,11 @@ def main():
     ci = torch.from_numpy(g.colidx).to(dev)
     out = torch.empty(g.n, dtype=torch.int32, device=dev)
 
-    G = gc.Graph(rp, ci, mode=args.mode, algorithm=args.algorithm, lanes=args.lanes)
+    extra = {"partitions": golden["blocks_p"]} if args.algorithm == "blocks" else {}
+    G = gc.Graph(rp, ci, mode=args.mode, algorithm=args.algorithm, lanes=args.lanes, **extra)
     tuned = None
-    if not args.no_autotune and args.lanes == 0:
+    # (the p-block colouring has none of the tuned knobs but the grid)
+    if not args.no_autotune and args.lanes == 0 and args.algorithm != "blocks":
         from paper_1509_08267_amd import autotune
         res = autotune.tune(G, budget_s=args.tune_budget)
         tuned = dict(res.setting, cached=res.cached, measurements=len(res.table),
@@ -137,6 +142,8 @@ def main():
     got = hashlib.sha256(out.cpu().numpy().astype(np.int32).tobytes()).hexdigest()
     if args.algorithm == "seq":
         parity = got == golden["seq_colors_sha256"] and rounds == golden["seq_rounds"]
+    elif args.algorithm == "blocks":
+        parity = got == golden["blocks_colors_sha256"] and rounds == golden["blocks_rounds"]
     else:
         parity = got == golden["colors_sha256"] and rounds == golden["rounds"]
 
@@ -165,8 +172,8 @@ def main():
     prof = G.profile()
     G.set("profile", 0)
     sbytes = G.get(gc.GC_OPT_STATE_BYTES)
-    algo = {gc.GC_ALGO_PUSH: "push", gc.GC_ALGO_PULL: "pull",
-            gc.GC_ALGO_SEQ: "seq"}[G.get(gc.GC_OPT_ALGORITHM)]
+    algo = {gc.GC_ALGO_PUSH: "push", gc.GC_ALGO_PULL: "pull", gc.GC_ALGO_SEQ: "seq",
+            gc.GC_ALGO_BLOCKS: "blocks"}[G.get(gc.GC_OPT_ALGORITHM)]
     lanes = G.get(gc.GC_OPT_LANES)
     G_medium = G.get(gc.GC_OPT_MEDIUM_DEGREE)
     G_heavy = G.get(gc.GC_OPT_HEAVY_DEGREE)
@@ -227,23 +234,36 @@ def main():
                       * (4 + sbytes) + golden["seq_rows_after_round1"] * (4 + sbytes)
                       + sc * sbytes)
         det_bytes = sv * sbytes + sc * sbytes
+    # rounds whose kernels are timed per colouring (round 1 has its own launch
+    # except in the p-block colouring)
+    timed_rounds = rounds if algo == "blocks" else rounds - 1
+    if algo == "blocks":
+        # phase 1 ("speculate"): per pending vertex its rowptr pair, todo byte
+        # and colour write, per row entry the neighbour id and its slot or
+        # colour; phase 2 ("detect"): the same reads, per entry also the slot
+        # write (entries whose neighbour is in another block: all but ~0.2%
+        # at p = 16384), per pending vertex the todo write
+        sa, sd = golden["blocks_sum_active"], golden["blocks_sum_active_deg"]
+        spec_bytes = sd * 8 + sa * (2 * rp_b + 1 + 4)
+        det_bytes = sd * 12 + sa * (2 * rp_b + 1 + 4 + 1)
     spec_ms, spec_launches = prof["speculate"]
     det_ms, det_launches = prof["detect"]
     kernel = "detect" if det_ms > spec_ms else "speculate"
     k_ms, k_launches, k_bytes = ((det_ms, det_launches, det_bytes) if kernel == "detect"
                                  else (spec_ms, spec_launches, spec_bytes))
-    calls = max(1, k_launches // max(1, rounds - 1))
+    calls = max(1, k_launches // max(1, timed_rounds))
     achieved = k_bytes * calls / (k_ms / 1e3) / 1e9 if k_ms > 0 else None
     traffic = measured_traffic(args.workload, kernel)
     roofline = {
-        "kernel": kernel,
+        "kernel": ({"speculate": "k_blk_phase1", "detect": "k_blk_phase2"}[kernel]
+                   if algo == "blocks" else kernel),
         "bound": "hbm",
         "achieved": round(achieved, 1) if achieved else None,
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
         "traffic": traffic,
-        "alg_bytes_per_launch": k_bytes // max(1, rounds - 1),
+        "alg_bytes_per_launch": k_bytes // max(1, timed_rounds),
         "avg_launch_us": round(k_ms * 1e3 / max(1, k_launches), 2),
         "launches": k_launches,
         "other_kernel": {"kernel": "speculate" if kernel == "detect" else "detect",
@@ -263,7 +283,7 @@ def main():
     # over the timed step.
     pull_bytes = (8 * golden["sum_active_deg"] + 8 * golden["sum_active_lower_deg"]
                   + golden["sum_active"] * (2 * (4 + 2 * rp_b + 4) + 4))
-    step_roofline = None if algo == "seq" else {"definition": "pull-equivalent bytes per colouring",
+    step_roofline = None if algo in ("seq", "blocks") else {"definition": "pull-equivalent bytes per colouring",
                      "bytes": pull_bytes,
                      "achieved": round(pull_bytes / t_step / 1e9, 1), "unit": "GB/s",
                      "peak": HBM_PEAK_GBS,
@@ -277,12 +297,17 @@ def main():
         tstart = time.perf_counter()
         while len(ts) < 3 and (time.perf_counter() - tstart) < budget:
             t = time.perf_counter()
-            (oracle.seq if algo == "seq" else oracle.rsc)(g.rowptr, g.colidx)
+            if algo == "seq":
+                oracle.seq(g.rowptr, g.colidx)
+            elif algo == "blocks":
+                oracle.blocks(g.rowptr, g.colidx, golden["blocks_p"])
+            else:
+                oracle.rsc(g.rowptr, g.colidx)
             ts.append(time.perf_counter() - t)
         tb = min(ts)
         cpu = {"value": round(g.m / tb / 1e9, 5), "unit": "GTEPS", "cores": 1, "kind": "oracle",
                "sample": f"whole {args.workload} graph, oracle "
-                         f"{'seq' if algo == 'seq' else 'rsc'}, best of {len(ts)} single-thread runs "
+                         f"{algo if algo in ('seq', 'blocks') else 'rsc'}, best of {len(ts)} single-thread runs "
                          f"({tb:.2f} s each)",
                "seconds": round(tb, 3)}
 
@@ -307,6 +332,7 @@ def main():
         "colors": ncolors,
         "colors_seq": golden.get("seq_num_colors"),
         "rounds_seq": golden.get("seq_rounds"),
+        "partitions": golden["blocks_p"] if algo == "blocks" else None,
         "rounds": rounds,
         "parity_vs_oracle": parity,
         "first_call_ms": round(t_first * 1e3, 3),

@@ -491,7 +491,18 @@ static int color_blocks(gc_ctx* h, int32_t* colors_out, hipStream_t s) {
     if (h->profile) HIPCHECK(h, hipEventRecord(h->pev[1], s));
     for (int r = 1;; ++r) {
       b.round = r;
-      LCHECK(h, gc::launch_blocks_round(b, h->rp64, grid, s));
+      if (h->profile) {  // phase 1 and phase 2 between events, as speculate and detect
+        rc = reserve_round_events(h, r > h->rev_rounds ? std::max(r, 2 * h->rev_rounds) : r);
+        if (rc) return rc;
+        HIPCHECK(h, hipEventRecord(h->rev[3 * (r - 1)], s));
+      }
+      LCHECK(h, gc::launch_blocks_phase(b, h->rp64, 1, grid, s));
+      if (h->profile) HIPCHECK(h, hipEventRecord(h->rev[3 * (r - 1) + 1], s));
+      LCHECK(h, gc::launch_blocks_phase(b, h->rp64, 2, grid, s));
+      if (h->profile) {
+        HIPCHECK(h, hipEventRecord(h->rev[3 * (r - 1) + 2], s));
+        h->timed_rounds = r;
+      }
       HIPCHECK(h, hipMemcpyAsync(&h->host->flag, &h->ctrl->left.v, sizeof(int32_t),
                                  hipMemcpyDeviceToHost, s));
       HIPCHECK(h, hipStreamSynchronize(s));

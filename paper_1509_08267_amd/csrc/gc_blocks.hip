@@ -15,7 +15,8 @@
 //            recoloured").
 // Mapping: one wavefront per block in phase 1 (a block is sequential by
 // definition; the wavefront searches each row for the least absent colour
-// together), one lane per vertex in phase 2, a kernel boundary per barrier.
+// together), one wavefront per 64 consecutive vertices in phase 2, a kernel
+// boundary per barrier.
 //
 // The slot for a neighbour in the same block always equals that
 // neighbour's current colour (it is written whenever the neighbour is
@@ -84,6 +85,12 @@ __global__ __launch_bounds__(kBlock) void k_blk_phase1(BArgs a) {
   }
 }
 
+// Phase 2 by 64-vertex chunks: the rows of a chunk's pending vertices are
+// consecutive in colidx, so the wavefront streams them as one segmented
+// list (coalesced reads of colidx, coalesced slot writes); entry j belongs to
+// the last lane whose exclusive prefix is <= j (binary search over the
+// prefixes with cross-lane reads), and the conflicts of the chunk meet in a
+// 64-bit mask, bit i for lane i's vertex.
 template <typename RP>
 __global__ __launch_bounds__(kBlock) void k_blk_phase2(BArgs a) {
   __shared__ int sh_active, sh_lost;
@@ -94,25 +101,69 @@ __global__ __launch_bounds__(kBlock) void k_blk_phase2(BArgs a) {
   }
   __syncthreads();
   int active = 0, lost = 0;
-  const long tid = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  const long nth = (long)gridDim.x * blockDim.x;
-  for (long vl = tid; vl < a.n; vl += nth) {
-    const int v = (int)vl;
-    if (!a.todo[v]) continue;
-    const long b = (long)v * a.p / a.n;
-    const int v0 = block_start(b, a.n, a.p), v1 = block_start(b + 1, a.n, a.p);
-    const int cv = a.color[v];
-    bool lose = false;
-    for (RP k = rp[v]; k < rp[v + 1]; ++k) {
-      const int u = a.colidx[k];
-      if (u >= v0 && u < v1) continue;  // same block
-      const int cu = a.color[u];
-      a.slot[k] = cu;
-      lose |= cu == cv && u >= v1;  // u in a higher-numbered block
+  const int lane = lane_id();
+  const long wave_gid = blockIdx.x * (long)kWavesPerBlock + threadIdx.x / kWave;
+  const long nwaves = (long)gridDim.x * kWavesPerBlock;
+  const long nchunks = ((long)a.n + kWave - 1) / kWave;
+  for (long ch = wave_gid; ch < nchunks; ch += nwaves) {
+    const int v = (int)(ch * kWave) + lane;
+    const bool pend = v < a.n && a.todo[v];
+    RP b = 0;
+    int len = 0, v0 = 0, v1 = 0, cv = 0;
+    if (pend) {
+      b = rp[v];
+      len = (int)(rp[v + 1] - b);
+      const long blk = (long)v * a.p / a.n;
+      v0 = block_start(blk, a.n, a.p);
+      v1 = block_start(blk + 1, a.n, a.p);
+      cv = a.color[v];
     }
-    a.todo[v] = lose;
-    active += 1;
-    lost += lose;
+    if (__ballot(pend) == 0) continue;
+    int incl = len;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const int y = __shfl_up(incl, off);
+      if (lane >= off) incl += y;
+    }
+    const int total = __shfl(incl, kWave - 1);
+    const int excl = incl - len;
+    uint64_t lm = 0;
+    for (int j0 = 0; j0 < total; j0 += 4 * kWave) {
+      int u[4], o[4], ov1[4], ocv[4];
+      bool ok[4], foreign[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int j = j0 + q * kWave + lane;
+        ok[q] = j < total;
+        int lo = 0;
+#pragma unroll
+        for (int w = 32; w > 0; w >>= 1) {
+          const int mid = lo + w;
+          const int pm = __shfl(excl, mid < kWave ? mid : kWave - 1);
+          if (mid < kWave && pm <= j) lo = mid;
+        }
+        o[q] = lo;
+        const RP ob = shfl_any<RP>(b, lo);
+        const int oe = __shfl(excl, lo);
+        const int ov0 = __shfl(v0, lo);
+        ov1[q] = __shfl(v1, lo);
+        ocv[q] = __shfl(cv, lo);
+        u[q] = ok[q] ? a.colidx[ob + (j - oe)] : 0;
+        foreign[q] = ok[q] && (u[q] < ov0 || u[q] >= ov1[q]);
+        if (foreign[q]) {
+          const int cu = a.color[u[q]];
+          a.slot[ob + (j - oe)] = cu;
+          if (cu == ocv[q] && u[q] >= ov1[q]) lm |= 1ull << o[q];  // higher block
+        }
+      }
+    }
+    lm = group_or<kWave>(lm);
+    if (pend) {
+      const bool lose = (lm >> lane) & 1;
+      a.todo[v] = lose;
+      active += 1;
+      lost += lose;
+    }
   }
   if (active) atomicAdd(&sh_active, active);
   if (lost) atomicAdd(&sh_lost, lost);
@@ -131,13 +182,16 @@ __global__ void k_blk_clear_left(Ctrl* c) {
 }
 
 template <typename RP>
-static int launch_blocks_round_t(const BArgs& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_blk_clear_left, dim3(1), dim3(64), 0, s, a.ctrl);
-  // enough wavefronts for one per block, capped by the grid of the round kernels
-  const long waves = a.p;
-  const int g1 = (int)std::min<long>((waves + kWavesPerBlock - 1) / kWavesPerBlock, (long)grid);
-  hipLaunchKernelGGL((k_blk_phase1<RP>), dim3(std::max(1, g1)), dim3(kBlock), 0, s, a);
-  hipLaunchKernelGGL((k_blk_phase2<RP>), dim3(grid), dim3(kBlock), 0, s, a);
+static int launch_blocks_phase_t(const BArgs& a, int phase, int grid, hipStream_t s) {
+  if (phase == 1) {
+    hipLaunchKernelGGL(k_blk_clear_left, dim3(1), dim3(64), 0, s, a.ctrl);
+    // enough wavefronts for one per block, capped by the grid of the round kernels
+    const long waves = a.p;
+    const int g1 = (int)std::min<long>((waves + kWavesPerBlock - 1) / kWavesPerBlock, (long)grid);
+    hipLaunchKernelGGL((k_blk_phase1<RP>), dim3(std::max(1, g1)), dim3(kBlock), 0, s, a);
+  } else {
+    hipLaunchKernelGGL((k_blk_phase2<RP>), dim3(grid), dim3(kBlock), 0, s, a);
+  }
   return (int)hipGetLastError();
 }
 
@@ -157,9 +211,9 @@ int launch_blocks_init(const BArgs& a, bool rp64, int grid, void* stream) {
   return (int)hipGetLastError();
 }
 
-int launch_blocks_round(const BArgs& a, bool rp64, int grid, void* stream) {
-  return rp64 ? launch_blocks_round_t<int64_t>(a, grid, (hipStream_t)stream)
-              : launch_blocks_round_t<int32_t>(a, grid, (hipStream_t)stream);
+int launch_blocks_phase(const BArgs& a, bool rp64, int phase, int grid, void* stream) {
+  return rp64 ? launch_blocks_phase_t<int64_t>(a, phase, grid, (hipStream_t)stream)
+              : launch_blocks_phase_t<int32_t>(a, phase, grid, (hipStream_t)stream);
 }
 
 }  // namespace gc

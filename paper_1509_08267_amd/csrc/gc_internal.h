@@ -87,9 +87,10 @@ struct BArgs {
 };
 
 int launch_blocks_init(const BArgs& a, bool rp64, int grid, void* stream);
-// Phase 1, barrier, phase 2 of one round; ctrl->left receives the vertices
-// to recolour, ctrl->trace / last_round the round's size.
-int launch_blocks_round(const BArgs& a, bool rp64, int grid, void* stream);
+// Phase 1 (phase = 1) or phase 2 (phase = 2) of one round; after phase 2,
+// ctrl->left holds the vertices to recolour and ctrl->trace / last_round the
+// round's size.
+int launch_blocks_phase(const BArgs& a, bool rp64, int phase, int grid, void* stream);
 // ctrl->left = value (vertices still to recolour when a round cap stops the loop)
 int launch_blocks_set_left(Ctrl* c, int value, void* stream);
 

@@ -5,6 +5,7 @@ Every value in the output comes from ``graphgen`` (the inputs) and ``oracle``
 
     python tests/golden/make_golden.py [workload ...]
     python tests/golden/make_golden.py --seq-only [workload ...]
+    python tests/golden/make_golden.py --blocks-only [workload ...]
 
 Per workload it records the input's SHA-256 and shape, the oracle's round
 count, colour count and the SHA-256 of its colour vector, the per-round
@@ -141,6 +142,23 @@ def one(name):
     return rec
 
 
+BLOCKS_P = 16384  # blocks of the recorded p-block colourings (64 per CU on 256 CUs)
+
+
+def blocks_fields(g):
+    """Algorithm 1 read literally with BLOCKS_P blocks."""
+    t = time.perf_counter()
+    col, R, rec = oracle.blocks(g.rowptr, g.colidx, BLOCKS_P)
+    return {"blocks_p": BLOCKS_P, "blocks_seconds": time.perf_counter() - t,
+            "blocks_colors_sha256": colors_sha(col), "blocks_rounds": R,
+            "blocks_num_colors": int(col.max()) + 1 if col.size else 0,
+            "blocks_sum_active": int((rec.astype(np.int64) + 1).sum()),
+            # a vertex is pending in rounds 1 .. recolours + 1: the rows those
+            # rounds read
+            "blocks_sum_active_deg": int(((rec.astype(np.int64) + 1)
+                                          * np.diff(g.rowptr).astype(np.int64)).sum())}
+
+
 def seq_fields(g):
     """Sequential First Fit (the Section 5 baseline) and the rounds of the
     id-priority schedule that reproduces it."""
@@ -170,6 +188,16 @@ def main(names):
     if os.path.exists(OUT):
         with open(OUT) as f:
             data = json.load(f)
+    if names and names[0] == "--blocks-only":
+        # (re)compute only the p-block fields of recorded workloads
+        for name in names[1:] or ["er_10k_100k", "er_1m_16m"]:
+            g = graphgen.workload(name)
+            assert g.sha256() == data[name]["input_sha256"]
+            data[name].update(blocks_fields(g))
+            print(f"[golden] {name}: blocks rounds {data[name]['blocks_rounds']}", flush=True)
+        with open(OUT, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+        return
     if names and names[0] == "--seq-only":
         # refresh only the sequential-baseline fields of recorded workloads
         for name in names[1:] or [k for k in data if k != "er_batch_4096"]:
