@@ -273,6 +273,66 @@ def test_blocks_pins_reject_higher_partition_losing():
     assert flipped(adj(g), 7) != ([1] + [0] * 6, 2)
 
 
+# ---------------------------------------------------- orderings (future work) --
+
+def test_splitmix64_published_outputs():
+    from oracle import ordering
+    # the generator's first outputs from state 0 and from state 1234567, as
+    # printed with its published reference implementation
+    z = 0
+    out = []
+    for _ in range(3):
+        z = (z + ordering.GOLDEN_GAMMA) & ((1 << 64) - 1)
+        out.append(ordering.splitmix64_mix(z))
+    assert out[0] == 0xE220A8397B1DCDAF
+    assert out[1] == 0x6E789E6AA1B965F4
+    assert out[2] == 0x06C45D188009454F
+    z = 1234567
+    z = (z + ordering.GOLDEN_GAMMA) & ((1 << 64) - 1)
+    assert ordering.splitmix64_mix(z) == 6457827717110365317
+    # the vectorised keys are the same function
+    keys = ordering.random_keys(5, 99)
+    assert [int(k) for k in keys] == [
+        ordering.splitmix64_mix(99 + (v + 1) * ordering.GOLDEN_GAMMA) for v in range(5)]
+
+
+def test_largest_first_order():
+    from oracle import ordering
+    g = graphgen.from_edges(6, [(0, 1), (1, 2), (1, 3), (3, 4), (3, 5), (4, 5)])
+    # degrees 1,3,1,3,2,2: the two degree-3 vertices first (by id), then 4, 5, then 0, 2
+    assert list(ordering.order(g.rowptr, g.colidx, "largest_first")) == [1, 3, 4, 5, 0, 2]
+    for h in _random_graphs(200, 12, seed=41):
+        s = ordering.order(h.rowptr, h.colidx, "largest_first")
+        d = np.diff(h.rowptr)[s]
+        assert sorted(s) == list(range(h.n))
+        assert all(d[i] > d[i + 1] or (d[i] == d[i + 1] and s[i] < s[i + 1])
+                   for i in range(h.n - 1))
+
+
+def test_relabel_is_an_isomorphism_with_sorted_rows():
+    from oracle import ordering
+    for h in list(_random_graphs(100, 12, seed=42)) + [graphgen.er(500, 3000, 5)]:
+        for kind in ("largest_first", "random"):
+            s = ordering.order(h.rowptr, h.colidx, kind, seed=7)
+            rp2, ci2, newid = ordering.relabel(h.rowptr, h.colidx, s)
+            assert sorted(s) == list(range(h.n))
+            e1 = {(int(newid[v]), int(u2)) for v in range(h.n)
+                  for u2 in newid[h.colidx[h.rowptr[v]:h.rowptr[v + 1]]]}
+            e2 = {(i, int(u)) for i in range(h.n) for u in ci2[rp2[i]:rp2[i + 1]]}
+            assert e1 == e2
+            assert all(np.all(np.diff(ci2[rp2[i]:rp2[i + 1]]) > 0) for i in range(h.n))
+
+
+def test_largest_first_sequential_first_fit_on_a_star():
+    # the centre goes first: colour 0, every leaf 1 (natural order with the
+    # centre last gives the leaves 0 and the centre 1)
+    from oracle import ordering
+    g = graphgen.star(5, centre=5)
+    col, _ = ordering.colour_in_order(g.rowptr, g.colidx, "largest_first", 0, oracle.seq)
+    assert list(col) == [1, 1, 1, 1, 1, 0]
+    assert list(oracle.seq(g.rowptr, g.colidx)) == [0, 0, 0, 0, 0, 1]
+
+
 # ------------------------------------------------------ properties (random) --
 
 def _random_graphs(count, nmax, seed):
