@@ -167,7 +167,23 @@ enum gc_option {
                                 captured graph) with an event around every
                                 kernel; read with gc_get_profile           */
   GC_OPT_ALGORITHM = 14,     /* enum gc_algorithm (default GC_ALGO_AUTO)           */
-  GC_OPT_PARTITIONS = 15     /* p for GC_ALGO_BLOCKS; 0 = auto (64 per compute unit) */
+  GC_OPT_PARTITIONS = 15,    /* p for GC_ALGO_BLOCKS; 0 = auto (64 per compute unit) */
+  GC_OPT_ORDER = 16,         /* enum gc_order (default GC_ORDER_NATURAL)            */
+  GC_OPT_ORDER_SEED = 17     /* seed of GC_ORDER_RANDOM (default 0)                 */
+};
+/* The vertex order the colouring follows (the paper's future work names
+ * ordering schemes; its related work, Jones and Plassmann's random order).
+ * Vertex sigma[i] of the order is renamed i, the relabelled graph is
+ * coloured by the selected algorithm, and each vertex receives the colour of
+ * its new name.  Any order but NATURAL builds a relabelled copy of the CSR on
+ * the device at the next gc_color after the option changes (about 3x the
+ * CSR's size while it is built, then one copy; GC_ETOOBIG when nnz exceeds
+ * 2^31 - 1). */
+enum gc_order {
+  GC_ORDER_NATURAL = 0,        /* ids as given                                       */
+  GC_ORDER_LARGEST_FIRST = 1,  /* degree descending, ties by id                     */
+  GC_ORDER_RANDOM = 2          /* ascending by the splitmix64 generator's output at
+                                  step v + 1 from state GC_OPT_ORDER_SEED          */
 };
 /* The colouring to compute.  AUTO, PULL and PUSH compute the same colouring
  * (round-synchronous speculation, Algorithm 1 of Section 3.1 with every vertex

@@ -65,11 +65,22 @@ enum { kRound1 = 0, kSpecK = 1, kDetectK = 2, kFinishK = 3, kKinds = 4 };
 struct gc_ctx {
   int device = 0;
   int cus = 0;
-  const void* rowptr = nullptr;
+  const void* rowptr = nullptr;     // the graph coloured: the caller's, or its relabelled copy
   bool rp64 = false;
   const int32_t* colidx = nullptr;
   int64_t n = 0, m = 0;
   uint32_t flags = 0;
+  const void* rowptr_in = nullptr;  // the caller's CSR (borrowed) and flags
+  const int32_t* colidx_in = nullptr;
+  uint32_t flags_in = 0;
+  int order = GC_ORDER_NATURAL;     // requested vertex order and seed
+  uint64_t order_seed = 0;
+  int built_order = GC_ORDER_NATURAL;  // order of the graph currently bound
+  uint64_t built_seed = 0;
+  void* o_rowptr = nullptr;         // device: relabelled CSR, new ids, colours by new id
+  int32_t* o_colidx = nullptr;
+  int32_t* o_newid = nullptr;
+  int32_t* o_colors = nullptr;
 
   Ctrl* ctrl = nullptr;       // device
   void* state = nullptr;      // device, n * sbytes
@@ -257,6 +268,10 @@ static void free_ctx(gc_ctx* h) {
   if (h->wide) (void)hipFree(h->wide);
   if (h->widx) (void)hipFree(h->widx);
   if (h->skip) (void)hipFree(h->skip);
+  if (h->o_rowptr) (void)hipFree(h->o_rowptr);
+  if (h->o_colidx) (void)hipFree(h->o_colidx);
+  if (h->o_newid) (void)hipFree(h->o_newid);
+  if (h->o_colors) (void)hipFree(h->o_colors);
   if (h->bslot) (void)hipFree(h->bslot);
   if (h->btodo) (void)hipFree(h->btodo);
   if (h->host) (void)hipHostFree(h->host);
@@ -278,12 +293,12 @@ extern "C" int gc_create(gc_handle* out, const void* rowptr, const int32_t* coli
 
   gc_ctx* h = new (std::nothrow) gc_ctx();
   if (!h) return set_err(nullptr, GC_ENOMEM, "gc_create: out of host memory");
-  h->rowptr = rowptr;
+  h->rowptr = h->rowptr_in = rowptr;
   h->rp64 = (flags & GC_ROWPTR_I64) != 0;
-  h->colidx = colidx;
+  h->colidx = h->colidx_in = colidx;
   h->n = n;
   h->m = m;
-  h->flags = flags;
+  h->flags = h->flags_in = flags;
   hipStream_t s = (hipStream_t)stream;
 
 #define CREATE_CHECK(expr)                                                                      \
@@ -461,10 +476,55 @@ static void collect_profile(gc_ctx* h) {
   h->timed_rounds = 0;
 }
 
+// Bind the graph in the requested vertex order: the caller's CSR, or a
+// relabelled copy built on the device (set-up work, synchronous).
+static int ensure_order(gc_ctx* h, hipStream_t s) {
+  if (h->order == h->built_order &&
+      (h->order != GC_ORDER_RANDOM || h->order_seed == h->built_seed))
+    return GC_OK;
+  int rc = ensure_idle(h);
+  if (rc) return rc;
+  for (void* p : {h->o_rowptr, (void*)h->o_colidx, (void*)h->o_newid, (void*)h->o_colors})
+    if (p) (void)hipFree(p);
+  h->o_rowptr = nullptr;
+  h->o_colidx = h->o_newid = h->o_colors = nullptr;
+  h->rowptr = h->rowptr_in;
+  h->colidx = h->colidx_in;
+  h->flags = h->flags_in;
+  h->built_order = GC_ORDER_NATURAL;
+  h->lists_dirty = true;
+  h->known_rounds = 0;
+  if (h->order == GC_ORDER_NATURAL) return GC_OK;
+  if (h->m > INT32_MAX)
+    return set_err(h, GC_ETOOBIG, "vertex order: more than 2^31 - 1 CSR entries");
+  const size_t nv = (size_t)std::max<int64_t>(h->n, 1);
+  hipError_t e = hipMalloc(&h->o_rowptr, (nv + 1) * (h->rp64 ? 8 : 4));
+  if (e == hipSuccess) e = hipMalloc((void**)&h->o_colidx, (size_t)std::max<int64_t>(h->m, 1) * 4);
+  if (e == hipSuccess) e = hipMalloc((void**)&h->o_newid, nv * 4);
+  if (e == hipSuccess) e = hipMalloc((void**)&h->o_colors, nv * 4);
+  if (e != hipSuccess) return set_err(h, GC_ENOMEM, "vertex order: %s", hipGetErrorString(e));
+  LCHECK(h, gc::build_order(h->rowptr_in, h->rp64, h->colidx_in, (int32_t)h->n, h->m, h->order,
+                            h->order_seed, h->o_rowptr, h->o_colidx, h->o_newid, grid_of(h), s));
+  h->rowptr = h->o_rowptr;
+  h->colidx = h->o_colidx;
+  h->flags = h->flags_in | GC_ROWS_SORTED;  // the relabelled rows are ascending
+  h->built_order = h->order;
+  h->built_seed = h->order_seed;
+  return GC_OK;
+}
+
+// The colours by new id go back to the caller's ids (no-op in natural order).
+static int permute_back(gc_ctx* h, const int32_t* coloured, int32_t* colors_out, hipStream_t s) {
+  if (coloured == colors_out || h->n == 0) return GC_OK;
+  LCHECK(h, gc::launch_permute_back(h->o_newid, coloured, (int32_t)h->n, colors_out,
+                                    std::min(grid_of(h), 4096), s));
+  return GC_OK;
+}
+
 // Algorithm 1 with p blocks (GC_ALGO_BLOCKS): per-edge slots, p sequential
 // blocks per round; the host reads the count of vertices to recolour after
 // each round (R <= p).
-static int color_blocks(gc_ctx* h, int32_t* colors_out, hipStream_t s) {
+static int color_blocks(gc_ctx* h, int32_t* colors_out, int32_t* user_out, hipStream_t s) {
   int rc = GC_OK;
   if (h->n > 0 && !h->bslot) {
     hipError_t e = hipMalloc((void**)&h->bslot, (size_t)std::max<int64_t>(h->m, 1) * sizeof(int32_t));
@@ -522,6 +582,8 @@ static int color_blocks(gc_ctx* h, int32_t* colors_out, hipStream_t s) {
   HIPCHECK(h, hipMemcpyAsync(&h->host->ncolors, &h->ctrl->ncolors.v, 4, hipMemcpyDeviceToHost, s));
   HIPCHECK(h, hipMemcpyAsync(&h->host->abort, &h->ctrl->abort.v, 4, hipMemcpyDeviceToHost, s));
   HIPCHECK(h, hipMemcpyAsync(&h->host->left, &h->ctrl->left.v, 4, hipMemcpyDeviceToHost, s));
+  rc = permute_back(h, colors_out, user_out, s);
+  if (rc) return rc;
   HIPCHECK(h, hipEventRecord(h->done, s));
   h->in_flight = true;
   h->stats_ready = true;
@@ -545,6 +607,10 @@ extern "C" int gc_color(gc_handle h, int32_t* colors_out, void* stream) {
     collect_profile(h);
   }
   if (h->in_flight) HIPCHECK(h, hipStreamWaitEvent(s, h->done, 0));
+  rc = ensure_order(h, s);
+  if (rc) return rc;
+  int32_t* const user_out = colors_out;
+  if (h->built_order != GC_ORDER_NATURAL) colors_out = h->o_colors;  // colours by new id
   if (h->lists_dirty) {
     rc = ensure_idle(h);
     if (rc) return rc;
@@ -552,7 +618,7 @@ extern "C" int gc_color(gc_handle h, int32_t* colors_out, void* stream) {
     if (rc) return rc;
   }
   (void)hipGetLastError();  // launch checks below must see only this call's errors
-  if (h->algorithm == GC_ALGO_BLOCKS) return color_blocks(h, colors_out, s);
+  if (h->algorithm == GC_ALGO_BLOCKS) return color_blocks(h, colors_out, user_out, s);
   if (use_push(h)) {
     if (!h->seen && h->n > 0) {
       hipError_t e = hipMalloc((void**)&h->seen, (size_t)h->n * gc::kPushColors);
@@ -662,6 +728,8 @@ extern "C" int gc_color(gc_handle h, int32_t* colors_out, void* stream) {
   HIPCHECK(h, hipMemcpyAsync(&h->host->ncolors, &h->ctrl->ncolors.v, 4, hipMemcpyDeviceToHost, s));
   HIPCHECK(h, hipMemcpyAsync(&h->host->abort, &h->ctrl->abort.v, 4, hipMemcpyDeviceToHost, s));
   HIPCHECK(h, hipMemcpyAsync(&h->host->left, &h->ctrl->left.v, 4, hipMemcpyDeviceToHost, s));
+  rc = permute_back(h, colors_out, user_out, s);
+  if (rc) return rc;
   HIPCHECK(h, hipEventRecord(h->done, s));
   h->in_flight = true;
   h->stats_ready = true;
@@ -764,6 +832,13 @@ extern "C" int gc_set_option(gc_handle h, int option, int64_t value) {
       if (family_of((int)value) != family_of(h->algorithm)) h->known_rounds = 0;
       h->algorithm = (int)value;
       return GC_OK;
+    case GC_OPT_ORDER:
+      if (value < GC_ORDER_NATURAL || value > GC_ORDER_RANDOM) break;
+      h->order = (int)value;
+      return GC_OK;
+    case GC_OPT_ORDER_SEED:
+      h->order_seed = (uint64_t)value;
+      return GC_OK;
     case GC_OPT_PARTITIONS:
       if (value < 0 || value > INT32_MAX) break;
       if (h->algorithm == GC_ALGO_BLOCKS) h->known_rounds = 0;
@@ -806,6 +881,8 @@ extern "C" int gc_get_option(gc_handle h, int option, int64_t* value) {
                                               : GC_ALGO_PULL;
       return GC_OK;
     case GC_OPT_PARTITIONS: *value = partitions_of(h); return GC_OK;
+    case GC_OPT_ORDER: *value = h->order; return GC_OK;
+    case GC_OPT_ORDER_SEED: *value = (int64_t)h->order_seed; return GC_OK;
     default: return set_err(h, GC_EINVAL, "gc_get_option: unknown option %d", option);
   }
 }

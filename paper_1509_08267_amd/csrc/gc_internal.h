@@ -94,6 +94,16 @@ int launch_blocks_phase(const BArgs& a, bool rp64, int phase, int grid, void* st
 // ctrl->left = value (vertices still to recolour when a round cap stops the loop)
 int launch_blocks_set_left(Ctrl* c, int value, void* stream);
 
+// Relabelling by a vertex order (gc_order.hip).  Writes the relabelled CSR
+// (rows ascending) into rowptr2 (n + 1 entries of the input's width) and
+// colidx2 (nnz), and newid[v] = the new id of v.  Synchronises `stream`.
+int build_order(const void* rowptr, bool rp64, const int32_t* colidx, int32_t n, int64_t nnz,
+                int kind, uint64_t seed, void* rowptr2, int32_t* colidx2, int32_t* newid, int grid,
+                void* stream);
+// out[v] = coloured[newid[v]]
+int launch_permute_back(const int32_t* newid, const int32_t* coloured, int32_t n, int32_t* out,
+                        int grid, void* stream);
+
 // Records `msg` as the calling thread's last error (gc_last_error(NULL)).
 void set_thread_error(const char* msg);
 

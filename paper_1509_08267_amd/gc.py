@@ -28,7 +28,11 @@ GC_ROWPTR_I64, GC_VALIDATE, GC_ROWS_SORTED = 1, 2, 4
 (GC_OPT_MODE, GC_OPT_LANES, GC_OPT_HEAVY_DEGREE, GC_OPT_BLOCKS_PER_CU, GC_OPT_MAX_ROUNDS,
  GC_OPT_CHUNK_ROUNDS, GC_OPT_MEDIUM_DEGREE, GC_OPT_MAX_DEGREE, GC_OPT_MEDIUM_COUNT,
  GC_OPT_HEAVY_COUNT, GC_OPT_PERSISTENT_BLOCKS_PER_CU, GC_OPT_STATE_BYTES,
- GC_OPT_PROFILE, GC_OPT_ALGORITHM, GC_OPT_PARTITIONS) = range(1, 16)
+ GC_OPT_PROFILE, GC_OPT_ALGORITHM, GC_OPT_PARTITIONS, GC_OPT_ORDER,
+ GC_OPT_ORDER_SEED) = range(1, 18)
+GC_ORDER_NATURAL, GC_ORDER_LARGEST_FIRST, GC_ORDER_RANDOM = range(3)
+ORDERS = {"natural": GC_ORDER_NATURAL, "largest_first": GC_ORDER_LARGEST_FIRST,
+          "random": GC_ORDER_RANDOM}
 GC_ALGO_AUTO, GC_ALGO_PULL, GC_ALGO_PUSH, GC_ALGO_SEQ, GC_ALGO_BLOCKS = range(5)
 ALGORITHMS = {"auto": GC_ALGO_AUTO, "pull": GC_ALGO_PULL, "push": GC_ALGO_PUSH,
               "seq": GC_ALGO_SEQ, "blocks": GC_ALGO_BLOCKS}
@@ -234,13 +238,16 @@ class Graph:
              "chunk_rounds": GC_OPT_CHUNK_ROUNDS, "medium_degree": GC_OPT_MEDIUM_DEGREE,
              "persistent_blocks_per_cu": GC_OPT_PERSISTENT_BLOCKS_PER_CU,
              "profile": GC_OPT_PROFILE, "algorithm": GC_OPT_ALGORITHM,
-             "partitions": GC_OPT_PARTITIONS}
+             "partitions": GC_OPT_PARTITIONS, "order": GC_OPT_ORDER,
+             "order_seed": GC_OPT_ORDER_SEED}
 
     def set(self, name: str, value):
         if name == "mode" and isinstance(value, str):
             value = MODES[value]
         if name == "algorithm" and isinstance(value, str):
             value = ALGORITHMS[value]
+        if name == "order" and isinstance(value, str):
+            value = ORDERS[value]
         gc_set_option(self.h, self._OPTS[name], value)
 
     def get(self, option: int) -> int:
