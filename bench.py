@@ -45,6 +45,9 @@ def parse():
                    help="keep the library's automatic settings instead of tuning them "
                         "(untimed) on the workload first")
     p.add_argument("--tune-budget", type=float, default=20.0)
+    p.add_argument("--order", default="natural", choices=["natural", "largest_first", "random"],
+                   help="vertex order (relabelled on the device, seed 0 for random); "
+                        "checked against the oracle's colouring in that order")
     p.add_argument("--batch-only", action="store_true",
                    help="batched workload: time the one-launch batch only (no per-graph "
                         "or served comparison); for profiling runs")
@@ -124,6 +127,10 @@ def main():
 
     extra = {"partitions": golden["blocks_p"]} if args.algorithm == "blocks" else {}
     G = gc.Graph(rp, ci, mode=args.mode, algorithm=args.algorithm, lanes=args.lanes, **extra)
+    if args.order != "natural":
+        if args.algorithm not in ("auto", "push", "pull"):
+            raise SystemExit("--order is recorded for the speculative colouring only")
+        G.set("order", args.order)
     tuned = None
     # (the p-block colouring has none of the tuned knobs but the grid)
     if not args.no_autotune and args.lanes == 0 and args.algorithm != "blocks":
@@ -144,6 +151,9 @@ def main():
         parity = got == golden["seq_colors_sha256"] and rounds == golden["seq_rounds"]
     elif args.algorithm == "blocks":
         parity = got == golden["blocks_colors_sha256"] and rounds == golden["blocks_rounds"]
+    elif args.order != "natural":
+        parity = (got == golden[f"order_{args.order}_colors_sha256"]
+                  and rounds == golden[f"order_{args.order}_rounds"])
     else:
         parity = got == golden["colors_sha256"] and rounds == golden["rounds"]
 
@@ -301,6 +311,10 @@ def main():
                 oracle.seq(g.rowptr, g.colidx)
             elif algo == "blocks":
                 oracle.blocks(g.rowptr, g.colidx, golden["blocks_p"])
+            elif args.order != "natural":
+                from oracle import ordering
+                ordering.colour_in_order(g.rowptr, g.colidx, args.order, 0,
+                                         lambda rp_, ci_: oracle.rsc(rp_, ci_).colors)
             else:
                 oracle.rsc(g.rowptr, g.colidx)
             ts.append(time.perf_counter() - t)
@@ -327,7 +341,7 @@ def main():
         "config": {"workload": args.workload, "n": g.n, "m": g.m, "nnz": g.nnz, "seed": 0,
                    "mode": args.mode, "algorithm": algo, "lanes": lanes, "state_bytes": sbytes,
                    "medium_degree": G_medium, "heavy_degree": G_heavy,
-                   "blocks_per_cu": G_bpc, "autotuned": tuned},
+                   "blocks_per_cu": G_bpc, "autotuned": tuned, "order": args.order},
         "vertices_per_s": round(g.n / t_step, 1),
         "colors": ncolors,
         "colors_seq": golden.get("seq_num_colors"),
@@ -338,8 +352,9 @@ def main():
         "first_call_ms": round(t_first * 1e3, 3),
         "profiled_ms_per_step": round(elapsed_prof / args.steps * 1e3, 4),
         "kernel_ms_per_step": kernels_ms_per_step,
-        "roofline": roofline,
-        "step_roofline_pull_equivalent": step_roofline,
+        # the byte counts are those of the natural order
+        "roofline": roofline if args.order == "natural" else None,
+        "step_roofline_pull_equivalent": step_roofline if args.order == "natural" else None,
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)

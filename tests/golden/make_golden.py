@@ -6,6 +6,7 @@ Every value in the output comes from ``graphgen`` (the inputs) and ``oracle``
     python tests/golden/make_golden.py [workload ...]
     python tests/golden/make_golden.py --seq-only [workload ...]
     python tests/golden/make_golden.py --blocks-only [workload ...]
+    python tests/golden/make_golden.py --orders-only [workload ...]
 
 Per workload it records the input's SHA-256 and shape, the oracle's round
 count, colour count and the SHA-256 of its colour vector, the per-round
@@ -145,6 +146,21 @@ def one(name):
 BLOCKS_P = 16384  # blocks of the recorded p-block colourings (64 per CU on 256 CUs)
 
 
+def order_fields(g):
+    """The speculative colouring in the largest-first and seed-0 random
+    vertex orders (relabel, colour, map back)."""
+    from oracle import ordering
+    rec = {}
+    for kind in ("largest_first", "random"):
+        col, (_, res) = ordering.colour_in_order(
+            g.rowptr, g.colidx, kind, 0, lambda rp, ci: (lambda r: (r.colors, r))(oracle.rsc(rp, ci)))
+        rec[f"order_{kind}_colors_sha256"] = colors_sha(col)
+        rec[f"order_{kind}_rounds"] = res.rounds
+        rec[f"order_{kind}_num_colors"] = res.num_colors
+        rec[f"order_{kind}_sum_active"] = int(res.trace[:, 0].sum())
+    return rec
+
+
 def blocks_fields(g):
     """Algorithm 1 read literally with BLOCKS_P blocks."""
     t = time.perf_counter()
@@ -188,6 +204,15 @@ def main(names):
     if os.path.exists(OUT):
         with open(OUT) as f:
             data = json.load(f)
+    if names and names[0] == "--orders-only":
+        for name in names[1:] or ["er_10k_100k", "er_1m_16m"]:
+            g = graphgen.workload(name)
+            assert g.sha256() == data[name]["input_sha256"]
+            data[name].update(order_fields(g))
+            print(f"[golden] {name}: orders", flush=True)
+        with open(OUT, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+        return
     if names and names[0] == "--blocks-only":
         # (re)compute only the p-block fields of recorded workloads
         for name in names[1:] or ["er_10k_100k", "er_1m_16m"]:
