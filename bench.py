@@ -321,7 +321,9 @@ def main():
         tb = min(ts)
         cpu = {"value": round(g.m / tb / 1e9, 5), "unit": "GTEPS", "cores": 1, "kind": "oracle",
                "sample": f"whole {args.workload} graph, oracle "
-                         f"{algo if algo in ('seq', 'blocks') else 'rsc'}, best of {len(ts)} single-thread runs "
+                         f"{algo if algo in ('seq', 'blocks') else 'rsc'}"
+                         f"{'' if args.order == 'natural' else ' after relabelling in the ' + args.order + ' order (numpy)'}"
+                         f", best of {len(ts)} single-thread runs "
                          f"({tb:.2f} s each)",
                "seconds": round(tb, 3)}
 

@@ -91,3 +91,28 @@ def test_orders_workload_er_1m(gc, kind):
     rp, ci = _dev(g)
     with gc.Graph(rp, ci) as G:
         check(gc, G, g, kind, 0, "push")
+
+
+@pytest.fixture(scope="module")
+def dense():
+    # dense ER: average degree 1000, 187 colours (past the 32 flag bytes, into
+    # the wide blocks of the wavefront-per-vertex path)
+    return graphgen.er(8000, 4000000, 17)
+
+
+@pytest.mark.parametrize("algo", ["push", "pull", "seq"])
+def test_dense_graph_natural_order(gc, dense, algo):
+    g = dense
+    want, R = ALGOS[algo](g.rowptr, g.colidx)
+    rp, ci = _dev(g)
+    with gc.Graph(rp, ci, algorithm=algo) as G:
+        for _ in range(2):
+            out = G.color()
+            r, k = G.stats()
+            assert r == R and np.array_equal(out.cpu().numpy(), want), algo
+
+
+def test_dense_graph_largest_first(gc, dense):
+    rp, ci = _dev(dense)
+    with gc.Graph(rp, ci) as G:
+        check(gc, G, dense, "largest_first", 0, "push")
