@@ -121,10 +121,27 @@ __device__ __forceinline__ void push_colour(const KArgs& a, const S* __restrict_
       if (st[u] < 0) a.seen[(size_t)u * kPushColors + t] = (uint8_t)epoch;
     }
   } else if (t < kPushColors + kWideColors) {
-    for (RP k = b + gl; k < e; k += step) {
+    // the same with the neighbour's wide-block index gathered beside its
+    // state (both depend only on the neighbour id)
+    const int c = t - kPushColors;
+    RP k = b + gl;
+    for (; k + 3 * (RP)step < e; k += 4 * (RP)step) {
+      int u[4], s[4], w[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) u[j] = a.colidx[k + j * step];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        s[j] = st[u[j]];
+        w[j] = a.widx[u[j]];
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (w[j] >= 0 && s[j] < 0) a.wide[(size_t)w[j] * kWideColors + c] = (uint8_t)epoch;
+    }
+    for (; k < e; k += step) {
       const int u = a.colidx[k];
       const int w = a.widx[u];
-      if (w >= 0 && st[u] < 0) a.wide[(size_t)w * kWideColors + (t - kPushColors)] = (uint8_t)epoch;
+      if (w >= 0 && st[u] < 0) a.wide[(size_t)w * kWideColors + c] = (uint8_t)epoch;
     }
   }
 }
@@ -214,6 +231,46 @@ __device__ __forceinline__ bool detect_group_skip(const int32_t* __restrict__ co
     if (pm) {
       *skip = first >= 0 ? first : (int)(kb - b) + __builtin_ctzll(pm);
       return false;
+    }
+  }
+  *skip = first >= 0 ? first : (int)(e - b);
+  return false;
+}
+
+// detect_group_skip for one vertex by a whole wavefront with four entries
+// per lane in flight: each step covers 256 entries as four sub-ranges of 64,
+// visited in order, so the first uncoloured entry, the first conflict and
+// the end of the lower prefix are found exactly as with 64-entry steps.
+template <typename RP, typename S>
+__device__ __forceinline__ bool detect_wave4_skip(const int32_t* __restrict__ colidx,
+                                                  const S* __restrict__ st, RP b, RP e, int v,
+                                                  int t, int lane, int* skip) {
+  int first = -1;
+  for (RP kb = b + *skip; kb < e; kb += 4 * kWave) {
+    int u[4], s[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const RP k = kb + j * kWave + lane;
+      u[j] = k < e ? colidx[k] : INT32_MAX;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) s[j] = u[j] < v ? (int)st[u[j]] : 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const bool low = u[j] < v;
+      const uint64_t am = __ballot(low && s[j] < 0);
+      const uint64_t cm = __ballot(low && tent_of(s[j]) == t);
+      const uint64_t pm = __ballot(!low);
+      const int base = (int)(kb - b) + j * kWave;
+      if (first < 0 && am) first = base + __builtin_ctzll(am);
+      if (cm) {
+        *skip = first >= 0 ? first : base + __builtin_ctzll(cm);
+        return true;
+      }
+      if (pm) {
+        *skip = first >= 0 ? first : base + __builtin_ctzll(pm);
+        return false;
+      }
     }
   }
   *skip = first >= 0 ? first : (int)(e - b);

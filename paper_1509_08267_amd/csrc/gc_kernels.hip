@@ -44,7 +44,7 @@ enum { kSpec = 0, kDetect = 1 };
 
 struct HeavySmem {
   uint32_t bm[kHeavyWindow / 32];
-  uint64_t am[kWavesPerBlock], cm[kWavesPerBlock], pm[kWavesPerBlock];  // detect_block_skip
+  uint64_t am[4][kWavesPerBlock], cm[4][kWavesPerBlock], pm[4][kWavesPerBlock];  // detect_block_skip
   int first;
   int active;  // per-block tallies of a detect phase
   int lost;
@@ -121,44 +121,54 @@ __device__ bool detect_block(const int32_t* __restrict__ colidx, const S* __rest
   return false;
 }
 
-// detect_group_skip for one vertex by the whole block (sorted rows): the
-// waves' ballots of "uncoloured", "conflict" and "past the lower prefix" meet
-// in LDS, and every thread reads the first set position of each.  Every
-// thread returns the same result and *skip.
+// detect_group_skip for one vertex by the whole block (sorted rows), four
+// entries per thread in flight: a step covers 1,024 entries as four
+// sub-ranges of 256 visited in order.  The waves' ballots of "uncoloured",
+// "conflict" and "past the lower prefix" meet in LDS, and every thread reads
+// the first set position of each.  Every thread returns the same result and
+// *skip.
 template <typename RP, typename S>
 __device__ bool detect_block_skip(const int32_t* __restrict__ colidx, const S* __restrict__ st,
                                   RP b, RP e, int v, int t, int* skip, HeavySmem& sm) {
   const int tid = threadIdx.x;
   const int wv = tid / kWave;
   int first = -1;
-  for (RP kb = b + *skip; kb < e; kb += kBlock) {
-    const RP k = kb + tid;
-    bool act = false, conf = false, past = true;
-    if (k < e) {
-      const int u = colidx[k];
-      if (u < v) {
-        const int s = st[u];
-        act = s < 0;
-        conf = tent_of(s) == t;
-        past = false;
+  for (RP kb = b + *skip; kb < e; kb += 4 * kBlock) {
+    int u[4], s[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const RP k = kb + j * kBlock + tid;
+      u[j] = k < e ? colidx[k] : INT32_MAX;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) s[j] = u[j] < v ? (int)st[u[j]] : 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const bool low = u[j] < v;
+      const uint64_t am = __ballot(low && s[j] < 0);
+      const uint64_t cm = __ballot(low && tent_of(s[j]) == t);
+      const uint64_t pm = __ballot(!low);
+      if (lane_id() == 0) {
+        sm.am[j][wv] = am;
+        sm.cm[j][wv] = cm;
+        sm.pm[j][wv] = pm;
       }
     }
-    const uint64_t am = __ballot(act), cm = __ballot(conf), pm = __ballot(past);
-    if (lane_id() == 0) {
-      sm.am[wv] = am;
-      sm.cm[wv] = cm;
-      sm.pm[wv] = pm;
-    }
     __syncthreads();
-    int fa = -1, fc = -1, fp = -1;
+    int fa = -1, fc = -1, fp = -1;  // positions within the step, sub-range major
 #pragma unroll
-    for (int i = 0; i < kWavesPerBlock; ++i) {
-      if (fa < 0 && sm.am[i]) fa = i * kWave + __builtin_ctzll(sm.am[i]);
-      if (fc < 0 && sm.cm[i]) fc = i * kWave + __builtin_ctzll(sm.cm[i]);
-      if (fp < 0 && sm.pm[i]) fp = i * kWave + __builtin_ctzll(sm.pm[i]);
-    }
-    __syncthreads();  // the masks are rewritten next iteration
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int i = 0; i < kWavesPerBlock; ++i) {
+        const int pos = j * kBlock + i * kWave;
+        if (fa < 0 && sm.am[j][i]) fa = pos + __builtin_ctzll(sm.am[j][i]);
+        if (fc < 0 && sm.cm[j][i]) fc = pos + __builtin_ctzll(sm.cm[j][i]);
+        if (fp < 0 && sm.pm[j][i]) fp = pos + __builtin_ctzll(sm.pm[j][i]);
+      }
+    __syncthreads();  // the masks are rewritten next step
     const int off = (int)(kb - b);
+    // rows ascend, so lower entries (uncoloured or conflicting) all precede
+    // the first past entry
     if (first < 0 && fa >= 0) first = off + fa;
     if (fc >= 0) {
       *skip = first >= 0 ? first : off + fc;
@@ -357,7 +367,7 @@ __device__ void medium_phase(const KArgs& a, long wave_gid, long nwaves, Tally& 
         RP pb = b;
         if (a.sorted) {
           int sk = a.skip[vv];
-          lose = detect_group_skip<RP, S, kWave>(a.colidx, st, b, e, vv, t, lane, ~0ull, 0, &sk);
+          lose = detect_wave4_skip<RP, S>(a.colidx, st, b, e, vv, t, lane, &sk);
           if (lane == 0) a.skip[vv] = sk;
           pb = b + sk;
         } else {
