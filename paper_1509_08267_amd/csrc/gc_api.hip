@@ -225,6 +225,18 @@ static KArgs make_args(const gc_ctx* h, int32_t* colors, int light_max) {
 
 static int grid_of(const gc_ctx* h) { return std::max(1, h->cus * h->blocks_per_cu); }
 
+// Workgroups of the round kernels: at most blocks_per_cu per CU, and no more
+// than the graph can keep busy (a wavefront per 64-vertex chunk or per medium
+// vertex, a workgroup per heavy vertex), so a small graph does not pay for
+// dispatching thousands of idle workgroups every round.
+static int round_grid(const gc_ctx* h) {
+  const int64_t chunks = (h->n + gc::kWave - 1) / gc::kWave;
+  const int64_t waves = std::max<int64_t>(chunks, h->mcount);
+  const int64_t blocks = std::max<int64_t>((waves + gc::kWavesPerBlock - 1) / gc::kWavesPerBlock,
+                                           h->hcount);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(grid_of(h), blocks));
+}
+
 // Build the medium and heavy lists for the current thresholds; synchronous.
 static int classify(gc_ctx* h, hipStream_t s) {
   const int L = auto_lanes(h);
@@ -389,8 +401,8 @@ static int capture(gc_ctx* h, Captured& c, const KArgs& a, int L, int K) {
   }
   int rc = 0;
   for (int j = 0; j < K && !rc; ++j) {
-    rc = gc::launch_round(a, h->rp64, h->sbytes, L, 0, j, true, grid_of(h), cs);
-    if (!rc) rc = gc::launch_round(a, h->rp64, h->sbytes, L, 1, j, true, grid_of(h), cs);
+    rc = gc::launch_round(a, h->rp64, h->sbytes, L, 0, j, true, round_grid(h), cs);
+    if (!rc) rc = gc::launch_round(a, h->rp64, h->sbytes, L, 1, j, true, round_grid(h), cs);
   }
   if (!rc) rc = gc::launch_advance_base(a, K, cs);
   hipGraph_t g = nullptr;
@@ -413,7 +425,7 @@ static int capture(gc_ctx* h, Captured& c, const KArgs& a, int L, int K) {
   c.exec = x;
   c.k = K;
   c.lanes = L;
-  c.grid = grid_of(h);
+  c.grid = round_grid(h);
   c.args = a;
   return GC_OK;
 }
@@ -543,7 +555,7 @@ static int color_blocks(gc_ctx* h, int32_t* colors_out, int32_t* user_out, hipSt
   b.n = (int32_t)h->n;
   b.p = partitions_of(h);
   b.ctrl = h->ctrl;
-  const int grid = grid_of(h);
+  const int grid = round_grid(h);
   LCHECK(h, gc::launch_init(a, s));
   if (h->profile) HIPCHECK(h, hipEventRecord(h->pev[0], s));
   if (h->n > 0) {
@@ -645,7 +657,7 @@ extern "C" int gc_color(gc_handle h, int32_t* colors_out, void* stream) {
   const int L = auto_lanes(h);
   const int light = light_max_of(h, L);
   const KArgs a = make_args(h, colors_out, light);
-  const int grid = grid_of(h);
+  const int grid = round_grid(h);
   const int mode = resolve_mode(h);
 
   LCHECK(h, gc::launch_init(a, s));
