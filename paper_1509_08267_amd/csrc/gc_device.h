@@ -182,65 +182,10 @@ __device__ __forceinline__ uint32_t taken_colours(const uint8_t* seen, int v, in
   return m;
 }
 
-// Conflict scan with a skip offset (sorted rows): starting at b + *skip,
-// does a lower-id neighbour of v that is still uncoloured carry tentative
-// colour t?  Group of L lanes (gl = lane in group, gmask = the group's lanes
-// in the wave ballot, gbase = the group's first lane).  On return *skip is
-// the offset of the first still-uncoloured lower neighbour seen, or of the
-// point where the scan ended when it saw none: every lower neighbour before
-// it is final, and final colours never change, so later rounds (and the
-// winner's pushes) may start there.
-template <typename RP, typename S, int L>
-__device__ __forceinline__ bool detect_group_skip(const int32_t* __restrict__ colidx,
-                                                  const S* __restrict__ st, RP b, RP e, int v,
-                                                  int t, int gl, uint64_t gmask, int gbase,
-                                                  int* skip) {
-  int first = -1;
-  RP kb = b + *skip;
-  for (; kb < e; kb += L) {
-    const RP k = kb + gl;
-    bool act = false, conf = false, past = false;
-    if (k < e) {
-      const int u = colidx[k];
-      if (u < v) {
-        const int s = st[u];
-        act = s < 0;
-        // decode, do not test the sign: a neighbour that wins in this same
-        // pass flips ~t to t concurrently and must still count; final
-        // colours of earlier rounds never equal t
-        conf = tent_of(s) == t;
-      } else {
-        past = true;
-      }
-    } else {
-      past = true;
-    }
-    if (first < 0) {
-      const uint64_t am = (__ballot(act) & gmask) >> gbase;
-      if (am) first = (int)(kb - b) + __builtin_ctzll(am);
-    }
-    if (__ballot(conf) & gmask) {
-      // entries before the first uncoloured one are final; when none was
-      // seen (the conflicting neighbour won in this pass) the scan may
-      // restart at the conflict next round
-      if (first < 0) first = (int)(kb - b) + __builtin_ctzll((__ballot(conf) & gmask) >> gbase);
-      *skip = first;
-      return true;
-    }
-    const uint64_t pm = (__ballot(past) & gmask) >> gbase;
-    if (pm) {
-      *skip = first >= 0 ? first : (int)(kb - b) + __builtin_ctzll(pm);
-      return false;
-    }
-  }
-  *skip = first >= 0 ? first : (int)(e - b);
-  return false;
-}
-
-// detect_group_skip for one vertex by a whole wavefront with four entries
-// per lane in flight: each step covers 256 entries as four sub-ranges of 64,
-// visited in order, so the first uncoloured entry, the first conflict and
-// the end of the lower prefix are found exactly as with 64-entry steps.
+// detect_lane_skip's scan for one vertex by a whole wavefront with four
+// entries per lane in flight: each step covers 256 entries as four
+// sub-ranges of 64, visited in order, so the first uncoloured entry, the
+// first conflict and the end of the lower prefix are found in row order.
 template <typename RP, typename S>
 __device__ __forceinline__ bool detect_wave4_skip(const int32_t* __restrict__ colidx,
                                                   const S* __restrict__ st, RP b, RP e, int v,
@@ -277,10 +222,15 @@ __device__ __forceinline__ bool detect_wave4_skip(const int32_t* __restrict__ co
   return false;
 }
 
-// The scan of detect_group_skip done by one lane for its own vertex, four
-// entries in flight: neighbour ids first, then the states of the lower ones.
-// Same result and the same guarantee on *skip (every lower neighbour before
-// it is final).
+// Conflict scan with a resume offset (sorted rows), by one lane for its own
+// vertex: starting at b + *skip, does a lower-id neighbour of v that is still
+// uncoloured carry tentative colour t?  The scan stops at the first conflict
+// or at the first neighbour id >= v.  On return *skip is the offset of the
+// first still-uncoloured lower neighbour seen, or of the point where the scan
+// ended when it saw none: every lower neighbour before it is final, and final
+// colours never change, so later rounds (and the winner's pushes) may start
+// there.  Four entries in flight: neighbour ids first, then the states of the
+// lower ones.
 template <typename RP, typename S>
 __device__ __forceinline__ bool detect_lane_skip(const int32_t* __restrict__ colidx,
                                                  const S* __restrict__ st, RP b, RP e, int v,
@@ -300,7 +250,10 @@ __device__ __forceinline__ bool detect_lane_skip(const int32_t* __restrict__ col
         return false;
       }
       if (first < 0 && s[j] < 0) first = off;
-      if (tent_of(s[j]) == t) {  // decoded, as in detect_group_skip
+      // decode, do not test the sign: a neighbour that wins in this same pass
+      // flips ~t to t concurrently and must still count; final colours of
+      // earlier rounds never equal t
+      if (tent_of(s[j]) == t) {
         *skip = first >= 0 ? first : off;
         return true;
       }

@@ -121,7 +121,7 @@ __device__ bool detect_block(const int32_t* __restrict__ colidx, const S* __rest
   return false;
 }
 
-// detect_group_skip for one vertex by the whole block (sorted rows), four
+// detect_lane_skip's scan for one vertex by the whole block (sorted rows), four
 // entries per thread in flight: a step covers 1,024 entries as four
 // sub-ranges of 256 visited in order.  The waves' ballots of "uncoloured",
 // "conflict" and "past the lower prefix" meet in LDS, and every thread reads
@@ -291,22 +291,15 @@ __device__ void light_phase(const KArgs& a, long wave_gid, long nwaves, Tally& t
           int t = spec_group<RP, S, L>(a.colidx, st, vb, ve, gl, push ? kPushColors : 0);
           if (gl == 0) st[vv] = (S)~t;
         } else {
+          // unsorted rows (sorted ones took the lane scan above): the whole
+          // row is scanned from its start
           const int t = ~vs;
-          bool lose;
-          RP pb = vb;  // winners push from here
-          if (sorted) {
-            int sk = a.skip[vv];
-            lose = detect_group_skip<RP, S, L>(a.colidx, st, vb, ve, vv, t, gl, gmask, grp * L, &sk);
-            if (gl == 0) a.skip[vv] = sk;
-            pb = vb + sk;
-          } else {
-            lose = detect_group<RP, S, L>(a.colidx, st, vb, ve, vv, t, gl, gmask, false);
-          }
+          const bool lose = detect_group<RP, S, L>(a.colidx, st, vb, ve, vv, t, gl, gmask, false);
           if (gl == 0) {
             if (!lose) st[vv] = (S)t;
             tl.lost += lose;
           }
-          if (push && !lose) push_colour<RP, S>(a, st, pb, ve, t, epoch, gl, L);
+          if (push && !lose) push_colour<RP, S>(a, st, vb, ve, t, epoch, gl, L);
         }
         if (gl == 0) tl.active += 1;
       }
@@ -385,23 +378,70 @@ __device__ void medium_phase(const KArgs& a, long wave_gid, long nwaves, Tally& 
 }
 
 // Is every lower-id neighbour of v final?  Whole block (heavy vertices).
+// Unsorted rows: the whole row, one entry per thread per step.
 template <typename RP, typename S>
 __device__ bool ready_block(const int32_t* __restrict__ colidx, const S* __restrict__ st,
-                            RP b, RP e, int v, bool sorted) {
+                            RP b, RP e, int v) {
   for (RP kb = b; kb < e; kb += kBlock) {
     const RP k = kb + threadIdx.x;
-    int wait = 0, past = 1;
+    int wait = 0;
     if (k < e) {
       const int u = colidx[k];
-      if (u < v) {
-        wait = st[u] < 0;
-        past = 0;
-      }
+      wait = u < v && st[u] < 0;
     }
     if (__syncthreads_or(wait)) return false;
-    if (sorted && __syncthreads_or(past)) return true;
   }
   return true;
+}
+
+// The same on sorted rows with the resume offset of the conflict scans:
+// from b + skip, four entries per thread per step (sub-ranges of 256 in
+// order).  Returns 2 * (new offset) + (1 if no lower neighbour is left that
+// is not final): the new offset is that of the first lower neighbour not yet
+// final, or where the lower prefix ends.  Every thread returns the same.
+// (The masks live in the function's own LDS arrays: taking the shared
+// HeavySmem by reference here made the gfx950 backend reject the code.)
+template <typename RP, typename S>
+__device__ __forceinline__ int ready_block_skip(const int32_t* __restrict__ colidx,
+                                                const S* __restrict__ st, RP b, RP e, int v,
+                                                int skip) {
+  __shared__ uint64_t wmask[4][kWavesPerBlock], pmask[4][kWavesPerBlock];
+  const int tid = threadIdx.x;
+  const int wv = tid / kWave;
+  for (RP kb = b + skip; kb < e; kb += 4 * kBlock) {
+    int u[4], s[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const RP k = kb + j * kBlock + tid;
+      u[j] = k < e ? colidx[k] : INT32_MAX;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) s[j] = u[j] < v ? (int)st[u[j]] : 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint64_t wm = __ballot(u[j] < v && s[j] < 0);
+      const uint64_t pm = __ballot(u[j] >= v);
+      if (lane_id() == 0) {
+        wmask[j][wv] = wm;
+        pmask[j][wv] = pm;
+      }
+    }
+    __syncthreads();
+    int fw = -1, fp = -1;  // positions within the step, sub-range major
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int i = 0; i < kWavesPerBlock; ++i) {
+        const int pos = j * kBlock + i * kWave;
+        if (fw < 0 && wmask[j][i]) fw = pos + __builtin_ctzll(wmask[j][i]);
+        if (fp < 0 && pmask[j][i]) fp = pos + __builtin_ctzll(pmask[j][i]);
+      }
+    __syncthreads();  // the masks are rewritten next step
+    const int off = (int)(kb - b);
+    if (fw >= 0) return 2 * (off + fw);  // lower entries all precede the first past entry
+    if (fp >= 0) return 2 * (off + fp) + 1;
+  }
+  return 2 * (int)(e - b) + 1;
 }
 
 template <typename RP, typename S, int PHASE>
@@ -418,7 +458,16 @@ __device__ void heavy_phase(const KArgs& a, long blk, long nblk, Tally& tl, Heav
     if (s >= 0 || skip) continue;  // block-uniform
     const RP b = rp[v], e = rp[v + 1];
     if (PHASE == kSpec && a.seq) {
-      if (ready_block<RP, S>(a.colidx, st, b, e, v, a.sorted != 0)) {
+      bool ready;
+      if (a.sorted) {
+        const int r2 = ready_block_skip<RP, S>(a.colidx, st, b, e, v, a.skip[v]);
+        ready = r2 & 1;
+        __syncthreads();  // every thread has read the old offset
+        if (threadIdx.x == 0) a.skip[v] = r2 >> 1;
+      } else {
+        ready = ready_block<RP, S>(a.colidx, st, b, e, v);
+      }
+      if (ready) {
         const int t = spec_block<RP, S>(a.colidx, st, b, e, sm, 0);
         if (threadIdx.x == 0) st[v] = (S)~t;
       }
