@@ -48,6 +48,8 @@ def parse():
     p.add_argument("--order", default="natural", choices=["natural", "largest_first", "random"],
                    help="vertex order (relabelled on the device, seed 0 for random); "
                         "checked against the oracle's colouring in that order")
+    p.add_argument("--rounds-per-step", type=int, default=4,
+                   help="served path: rounds each server step advances every resident job")
     p.add_argument("--batch-only", action="store_true",
                    help="batched workload: time the one-launch batch only (no per-graph "
                         "or served comparison); for profiling runs")
@@ -450,7 +452,7 @@ def run_batch(args, golden):
             self.colidx = cil[int(b.eoff[gi]):int(b.eoff[gi + 1])]
 
     reqs = [Req(gi) for gi in range(G)]
-    K = 4
+    K = args.rounds_per_step
     srv = serve.Server(budget_bytes=12 << 30, max_slots=G, rounds_per_step=K, keep_colors=False)
     t0 = time.perf_counter()
     jobs = srv.serve(reqs, np.zeros(G))
