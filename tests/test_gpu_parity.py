@@ -360,3 +360,30 @@ def test_options_changed_between_calls_on_one_handle(gc):
                 r, _ = G.stats()
                 assert r == ref.rounds, opts
                 assert np.array_equal(out.cpu().numpy(), ref.colors), opts
+
+
+def test_option_values_are_checked(gc):
+    # every option rejects values outside its range with GC_EINVAL and keeps
+    # its previous value; the handle still colours correctly afterwards
+    g = graphgen.er(3000, 20000, 13)
+    ref = oracle.rsc(g.rowptr, g.colidx)
+    rp, ci = _dev(g)
+    bad = [(gc.GC_OPT_MODE, 9), (gc.GC_OPT_LANES, 3), (gc.GC_OPT_LANES, 128),
+           (gc.GC_OPT_HEAVY_DEGREE, 0), (gc.GC_OPT_BLOCKS_PER_CU, 0),
+           (gc.GC_OPT_BLOCKS_PER_CU, 65), (gc.GC_OPT_MAX_ROUNDS, -1),
+           (gc.GC_OPT_CHUNK_ROUNDS, 0), (gc.GC_OPT_PERSISTENT_BLOCKS_PER_CU, 7),
+           (gc.GC_OPT_PROFILE, 2), (gc.GC_OPT_ALGORITHM, 5), (gc.GC_OPT_ALGORITHM, -1),
+           (gc.GC_OPT_PARTITIONS, -1), (gc.GC_OPT_ORDER, 3), (99, 0)]
+    with gc.Graph(rp, ci) as G:
+        before = {opt: G.get(opt) for opt, _ in bad if opt != 99}
+        for opt, val in bad:
+            with pytest.raises(gc.GCError) as e:
+                gc.gc_set_option(G.h, opt, val)
+            assert e.value.code == gc.GC_EINVAL, (opt, val)
+        for opt, v in before.items():
+            assert G.get(opt) == v, opt
+        with pytest.raises(gc.GCError):
+            G.get(99)
+        out = G.color()
+        assert G.stats()[0] == ref.rounds
+        assert np.array_equal(out.cpu().numpy(), ref.colors)
