@@ -39,11 +39,13 @@ struct Pinned {  // read-back area in pinned host memory
   int32_t pad0;
   int32_t counts[3];  // medium count, heavy count, max degree
   int32_t err[2];
-  int32_t last_round;
+  int32_t last_round;  // folded from fin by the host once a call has completed
   int32_t ncolors;
   int32_t abort;
   int32_t left;
-  int32_t pad1[3];
+  int32_t stale;
+  int32_t pad1[2];
+  int32_t fin[gc::kFinishWords];  // written by the finishing kernel (layout at launch_finish)
 };
 
 // One instantiated chunk of K rounds.  The graph holds the kernel arguments
@@ -93,8 +95,11 @@ struct gc_ctx {
   int64_t wide_blocks = 0;    // blocks allocated in `wide`
   int32_t* widx = nullptr;    // device, n: wide block of each medium/heavy vertex, -1 otherwise
   int32_t* skip = nullptr;    // device, n: final-prefix offset of each row (sorted rows)
+  uint64_t* low1 = nullptr;   // device, ceil(n / 64) words: round-1 losers (sorted rows)
+  int32_t* part = nullptr;    // device, cus * kMaxBlocksPerCu: per-workgroup round sizes
   int epoch = 0;              // epoch of the last call's pushed flags (1..255)
   Pinned* host = nullptr;     // pinned
+  int32_t* fin_dev = nullptr; // device address of host->fin
   int32_t mcount = 0, hcount = 0, maxdeg = 0;
 
   // options
@@ -219,6 +224,8 @@ static KArgs make_args(const gc_ctx* h, int32_t* colors, int light_max) {
   a.wide = h->wide;
   a.widx = h->widx;
   a.skip = h->skip;
+  a.low1 = h->low1;
+  a.part = h->part;
   a.ctrl = h->ctrl;
   return a;
 }
@@ -243,8 +250,10 @@ static int classify(gc_ctx* h, hipStream_t s) {
   const int light = light_max_of(h, L);
   const int heavy = std::max(h->heavy_min, light + 1);
   HIPCHECK(h, hipMemsetAsync(h->dcounts, 0, 3 * sizeof(int32_t), s));
-  LCHECK(h, gc::launch_classify(h->rowptr, h->rp64, (int32_t)h->n, light, heavy, h->mlist, h->hlist,
-                                h->dcounts, h->widx, grid_of(h), s));
+  const bool sorted = (h->flags & GC_ROWS_SORTED) != 0;
+  LCHECK(h, gc::launch_classify(h->rowptr, h->rp64, h->colidx, (int32_t)h->n, light, heavy,
+                                h->mlist, h->hlist, h->dcounts, h->widx,
+                                sorted ? h->low1 : nullptr, grid_of(h), s));
   HIPCHECK(h, hipMemcpyAsync(h->host->counts, h->dcounts, 3 * sizeof(int32_t),
                              hipMemcpyDeviceToHost, s));
   HIPCHECK(h, hipStreamSynchronize(s));
@@ -280,6 +289,8 @@ static void free_ctx(gc_ctx* h) {
   if (h->wide) (void)hipFree(h->wide);
   if (h->widx) (void)hipFree(h->widx);
   if (h->skip) (void)hipFree(h->skip);
+  if (h->low1) (void)hipFree(h->low1);
+  if (h->part) (void)hipFree(h->part);
   if (h->o_rowptr) (void)hipFree(h->o_rowptr);
   if (h->o_colidx) (void)hipFree(h->o_colidx);
   if (h->o_newid) (void)hipFree(h->o_newid);
@@ -333,7 +344,10 @@ extern "C" int gc_create(gc_handle* out, const void* rowptr, const int32_t* coli
   CREATE_CHECK(hipMalloc((void**)&h->dcounts, 8 * sizeof(int32_t)));
   CREATE_CHECK(hipMalloc((void**)&h->widx, (size_t)std::max<int64_t>(n, 1) * sizeof(int32_t)));
   CREATE_CHECK(hipMalloc((void**)&h->skip, (size_t)std::max<int64_t>(n, 1) * sizeof(int32_t)));
+  CREATE_CHECK(hipMalloc((void**)&h->low1, (size_t)std::max<int64_t>((n + 63) / 64, 1) * 8));
+  CREATE_CHECK(hipMalloc((void**)&h->part, (size_t)h->cus * gc::kMaxBlocksPerCu * sizeof(int32_t)));
   CREATE_CHECK(hipHostMalloc((void**)&h->host, sizeof(Pinned), hipHostMallocDefault));
+  CREATE_CHECK(hipHostGetDevicePointer((void**)&h->fin_dev, h->host->fin, 0));
   CREATE_CHECK(hipEventCreateWithFlags(&h->done, hipEventDisableTiming));
   memset(h->host, 0, sizeof(Pinned));
 
@@ -440,7 +454,7 @@ static bool usable(const Captured& c, int K, int L, int grid, const KArgs& a) {
          b.mlist == a.mlist && b.mcount == a.mcount && b.hlist == a.hlist &&
          b.hcount == a.hcount && b.sorted == a.sorted && b.push == a.push && b.seq == a.seq &&
          b.seen == a.seen && b.wide == a.wide && b.widx == a.widx && b.skip == a.skip &&
-         b.ctrl == a.ctrl;
+         b.low1 == a.low1 && b.part == a.part && b.ctrl == a.ctrl;
 }
 
 static float elapsed(hipEvent_t a, hipEvent_t b) {
@@ -584,16 +598,12 @@ static int color_blocks(gc_ctx* h, int32_t* colors_out, int32_t* user_out, hipSt
   } else if (h->profile) {
     HIPCHECK(h, hipEventRecord(h->pev[1], s));
   }
-  if (h->profile) HIPCHECK(h, hipEventRecord(h->pev[2], s));
-  LCHECK(h, gc::launch_finish(a, 4, std::min(grid, 1024), s));
   // a round cap can stop the loop with coloured vertices still in conflict
   if (h->n > 0 && h->host->flag) LCHECK(h, gc::launch_blocks_set_left(h->ctrl, h->host->flag, s));
+  if (h->profile) HIPCHECK(h, hipEventRecord(h->pev[2], s));
+  LCHECK(h, gc::launch_finish(a, 4, h->fin_dev, s));
   if (h->profile) HIPCHECK(h, hipEventRecord(h->pev[3], s));
   h->pending_profile = h->profile;
-  HIPCHECK(h, hipMemcpyAsync(&h->host->last_round, &h->ctrl->last_round.v, 4, hipMemcpyDeviceToHost, s));
-  HIPCHECK(h, hipMemcpyAsync(&h->host->ncolors, &h->ctrl->ncolors.v, 4, hipMemcpyDeviceToHost, s));
-  HIPCHECK(h, hipMemcpyAsync(&h->host->abort, &h->ctrl->abort.v, 4, hipMemcpyDeviceToHost, s));
-  HIPCHECK(h, hipMemcpyAsync(&h->host->left, &h->ctrl->left.v, 4, hipMemcpyDeviceToHost, s));
   rc = permute_back(h, colors_out, user_out, s);
   if (rc) return rc;
   HIPCHECK(h, hipEventRecord(h->done, s));
@@ -733,13 +743,9 @@ extern "C" int gc_color(gc_handle h, int32_t* colors_out, void* stream) {
     }
   }
   if (h->profile) HIPCHECK(h, hipEventRecord(h->pev[2], s));
-  LCHECK(h, gc::launch_finish(a, h->sbytes, std::min(grid, 1024), s));
+  LCHECK(h, gc::launch_finish(a, h->sbytes, h->fin_dev, s));
   if (h->profile) HIPCHECK(h, hipEventRecord(h->pev[3], s));
   h->pending_profile = h->profile && mode != GC_MODE_PERSISTENT;
-  HIPCHECK(h, hipMemcpyAsync(&h->host->last_round, &h->ctrl->last_round.v, 4, hipMemcpyDeviceToHost, s));
-  HIPCHECK(h, hipMemcpyAsync(&h->host->ncolors, &h->ctrl->ncolors.v, 4, hipMemcpyDeviceToHost, s));
-  HIPCHECK(h, hipMemcpyAsync(&h->host->abort, &h->ctrl->abort.v, 4, hipMemcpyDeviceToHost, s));
-  HIPCHECK(h, hipMemcpyAsync(&h->host->left, &h->ctrl->left.v, 4, hipMemcpyDeviceToHost, s));
   rc = permute_back(h, colors_out, user_out, s);
   if (rc) return rc;
   HIPCHECK(h, hipEventRecord(h->done, s));
@@ -748,14 +754,39 @@ extern "C" int gc_color(gc_handle h, int32_t* colors_out, void* stream) {
   return GC_OK;
 }
 
+// The finishing kernel's words, folded into the call's statistics.
+static void fold_finish(gc_ctx* h) {
+  Pinned* p = h->host;
+  const int32_t* f = p->fin;
+  p->last_round = f[0];
+  p->abort = f[1];
+  p->stale = f[4];
+  const int g = std::min(std::max(f[3], 0), gc::kFinishBlocks);
+  int32_t nc = 0;
+  int64_t left = f[2];
+  for (int b = 0; b < g; ++b) {
+    nc = std::max(nc, f[gc::kFinishHeader + 2 * b]);
+    left += f[gc::kFinishHeader + 1 + 2 * b];
+  }
+  p->ncolors = nc;
+  p->left = (int32_t)std::min<int64_t>(left, INT32_MAX);
+}
+
 static int wait_done(gc_ctx* h) {
   if (!h->stats_ready) return set_err(h, GC_EINVAL, "no colouring has been run on this handle");
   if (h->in_flight) {
     HIPCHECK(h, hipEventSynchronize(h->done));
     h->in_flight = false;
   }
+  fold_finish(h);  // the call has completed (also when another path waited for it)
   collect_profile(h);
   if (h->host->abort) return set_err(h, GC_EDEVICE, "persistent kernel: grid barrier timed out");
+  if (h->host->stale) {  // the set-up data (degree classes, round-1 bitmap) is rebuilt next call
+    h->lists_dirty = true;
+    h->known_rounds = 0;
+    return set_err(h, GC_EINVAL, "a vertex coloured in round 1 has a lower neighbour: the graph "
+                   "changed after gc_create");
+  }
   if (h->host->left) {
     if (h->max_rounds > 0 && h->host->last_round >= h->max_rounds)
       return set_err(h, GC_EROUNDS, "round cap reached with %d vertices uncoloured", h->host->left);
@@ -822,7 +853,7 @@ extern "C" int gc_set_option(gc_handle h, int option, int64_t value) {
       h->lists_dirty = true;
       return GC_OK;
     case GC_OPT_BLOCKS_PER_CU:
-      if (value < 1 || value > 64) break;
+      if (value < 1 || value > gc::kMaxBlocksPerCu) break;
       h->blocks_per_cu = (int)value;
       return GC_OK;
     case GC_OPT_MAX_ROUNDS:

@@ -30,6 +30,7 @@
 // each XCD.  A final pass widens it into the caller's int32 colours.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <cstdint>
 
@@ -521,11 +522,38 @@ __device__ void publish_detect(const KArgs& a, int r, const Tally& tl, HeavySmem
   __syncthreads();
   if (threadIdx.x == 0) {
     if (sm.lost) a.ctrl->more[(r + 1) % 3].v = 1;
-    if (sm.active) {
-      a.ctrl->last_round.v = r;
-      if (r - 1 < kTraceRounds) atomicAdd(&a.ctrl->trace[r - 1], sm.active);
+    if (sm.active) a.ctrl->last_round.v = r;
+    // the round's size: one count per workgroup with a plain store, folded
+    // by the next pass (same-address device atomics from every workgroup
+    // would queue up at the end of the pass)
+    a.part[blockIdx.x] = sm.active;
+    if (blockIdx.x == 0) {
+      a.ctrl->pend.v = r;
+      a.ctrl->pend_grid.v = (int)gridDim.x;
     }
   }
+}
+
+// Sum of the per-workgroup counts of the last detect pass into the round
+// trace.  Run by every thread of one workgroup, after the kernel boundary (or
+// grid barrier) that follows that pass.
+__device__ void fold_trace(const KArgs& a) {
+  __shared__ int sh[kWavesPerBlock];
+  const int r = a.ctrl->pend.v;
+  if (r == 0) return;
+  const int g = a.ctrl->pend_grid.v;
+  int sum = 0;
+  for (int i = threadIdx.x; i < g; i += blockDim.x) sum += a.part[i];
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+  if (lane_id() == 0) sh[threadIdx.x / kWave] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kWavesPerBlock; ++w) sum += sh[w];
+    if (r - 1 < kTraceRounds) a.ctrl->trace[r - 1] = sum;
+    a.ctrl->pend.v = 0;
+  }
+  __syncthreads();
 }
 
 // A whole phase of round r over every uncoloured vertex, by one block of a
@@ -549,6 +577,7 @@ template <typename RP, typename S, int L, int PHASE>
 __global__ __launch_bounds__(kBlock) void k_phase(KArgs a, int round, int from_base) {
   __shared__ HeavySmem sm;
   const int r = from_base ? a.ctrl->round_base.v + round : round;
+  if (PHASE == kSpec && blockIdx.x == 0) fold_trace(a);
   if (!a.ctrl->more[r % 3].v) {
     if (PHASE == kDetect && blockIdx.x == 0 && threadIdx.x == 0) a.ctrl->more[(r + 2) % 3].v = 0;
     return;
@@ -558,8 +587,13 @@ __global__ __launch_bounds__(kBlock) void k_phase(KArgs a, int round, int from_b
 
 // Round 1 in closed form for sorted rows: nothing is final, so every vertex
 // tries colour 0 and v keeps it exactly when no neighbour has a lower id,
-// i.e. when its first (smallest) neighbour is above v.  One lane per vertex
-// writes the whole state array, so no initialisation pass is needed.
+// i.e. when its first (smallest) neighbour is above v.  That outcome is a
+// property of the graph, recorded once per graph in the low1 bitmap, so the
+// pass reads one bit per vertex instead of a row sector.  A winner checks
+// the first entry of its own row (a few percent of the vertices) and flags a
+// graph changed since the bitmap was built; a stale loser bit only delays a
+// vertex.  One lane per vertex writes the whole state array, so no
+// initialisation pass is needed.
 template <typename RP, typename S>
 __global__ __launch_bounds__(kBlock) void k_round1_sorted(KArgs a) {
   __shared__ HeavySmem sm;
@@ -569,8 +603,11 @@ __global__ __launch_bounds__(kBlock) void k_round1_sorted(KArgs a) {
   const long tid = blockIdx.x * (long)blockDim.x + threadIdx.x;
   const long nth = (long)gridDim.x * blockDim.x;
   for (long v = tid; v < a.n; v += nth) {
-    const RP b = rp[v], e = rp[v + 1];
-    const bool lose = e > b && a.colidx[b] < v;
+    const bool lose = (a.low1[v / kWave] >> (v % kWave)) & 1;
+    if (!lose) {
+      const RP b = rp[v];
+      if (rp[v + 1] > b && a.colidx[b] < v) a.ctrl->stale.v = 1;
+    }
     st[v] = lose ? (S)-1 : (S)0;
     a.skip[v] = 0;
     tl.lost += lose;
@@ -601,15 +638,15 @@ __global__ __launch_bounds__(kBlock) void k_round1_sorted_push(KArgs a) {
     RP pb = 0;
     int len = 0;
     if (v < a.n) {
-      const RP b = rp[v], e = rp[v + 1];
-      const bool lose = e > b && a.colidx[b] < v;
+      const bool lose = (a.low1[ch] >> lane_id()) & 1;
       st[v] = lose ? (S)-1 : (S)0;
       a.skip[v] = 0;
       tl.lost += lose;
       tl.active += 1;
       if (!lose) {
-        pb = b;
-        len = (int)(e - b);
+        pb = rp[v];
+        len = (int)(rp[v + 1] - pb);
+        if (len > 0 && a.colidx[pb] < v) a.ctrl->stale.v = 1;
       }
     }
     push_flat<RP, S, false>(a, st, pb, len, 0, epoch);
@@ -649,7 +686,8 @@ __global__ void k_init(KArgs a) {
     a.ctrl->more[2].v = 0;
     a.ctrl->last_round.v = 0;
     a.ctrl->round_base.v = 2;
-    a.ctrl->ncolors.v = 0;
+    a.ctrl->stale.v = 0;
+    a.ctrl->pend.v = 0;
     a.ctrl->bar.v = 0;
     a.ctrl->abort.v = 0;
     a.ctrl->left.v = 0;
@@ -661,32 +699,65 @@ __global__ void k_advance_base(Ctrl* c, int by) {
   if (threadIdx.x == 0 && blockIdx.x == 0) c->round_base.v += by;
 }
 
-// Colour count, uncoloured count, and the widening of a narrow state into
-// the caller's int32 colours.
+__device__ __forceinline__ void store_system(int32_t* p, int32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Widening pass and statistics: the state becomes the caller's int32
+// colours, and each workgroup reports the largest colour and the uncoloured
+// count of its vertices straight into pinned host memory (layout at
+// launch_finish).  A few hundred workgroups, four loads in flight per thread,
+// and no device atomics: the host folds the per-workgroup pairs.
 template <typename S>
-__global__ __launch_bounds__(kBlock) void k_finish(KArgs a) {
-  __shared__ int sh_max, sh_left;
-  if (threadIdx.x == 0) {
-    sh_max = -1;
-    sh_left = 0;
-  }
-  __syncthreads();
+__global__ __launch_bounds__(kBlock) void k_finish(KArgs a, int32_t* out) {
+  __shared__ int sh_max[kWavesPerBlock], sh_left[kWavesPerBlock];
+  if (blockIdx.x == 0) fold_trace(a);  // the last detect pass's round size
+  constexpr int kU = 4;
   const S* __restrict__ st = (const S*)a.st;
   int mx = -1, left = 0;
-  const long tid = blockIdx.x * (long)blockDim.x + threadIdx.x;
   const long nth = (long)gridDim.x * blockDim.x;
-  for (long v = tid; v < a.n; v += nth) {
-    const int s = st[v];
-    a.colors[v] = s;
-    mx = s > mx ? s : mx;
-    left += s < 0;
+  for (long v0 = blockIdx.x * (long)blockDim.x + threadIdx.x; v0 < a.n; v0 += kU * nth) {
+    int s[kU];
+#pragma unroll
+    for (int q = 0; q < kU; ++q) {
+      const long v = v0 + q * nth;
+      s[q] = v < a.n ? (int)st[v] : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < kU; ++q) {
+      const long v = v0 + q * nth;
+      if (v < a.n) {
+        a.colors[v] = s[q];
+        mx = s[q] > mx ? s[q] : mx;
+        left += s[q] < 0;
+      }
+    }
   }
-  if (mx >= 0) atomicMax(&sh_max, mx);
-  if (left) atomicAdd(&sh_left, left);
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    const int om = __shfl_xor(mx, off);
+    mx = om > mx ? om : mx;
+    left += __shfl_xor(left, off);
+  }
+  if (lane_id() == 0) {
+    sh_max[threadIdx.x / kWave] = mx;
+    sh_left[threadIdx.x / kWave] = left;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
-    if (sh_max >= 0) atomicMax(&a.ctrl->ncolors.v, sh_max + 1);
-    if (sh_left) atomicAdd(&a.ctrl->left.v, sh_left);
+    for (int w = 1; w < kWavesPerBlock; ++w) {
+      mx = sh_max[w] > mx ? sh_max[w] : mx;
+      left += sh_left[w];
+    }
+    store_system(&out[kFinishHeader + 2 * blockIdx.x], mx + 1);
+    store_system(&out[kFinishHeader + 1 + 2 * blockIdx.x], left);
+    if (blockIdx.x == 0) {
+      store_system(&out[0], a.ctrl->last_round.v);
+      store_system(&out[1], a.ctrl->abort.v);
+      store_system(&out[2], a.ctrl->left.v);
+      store_system(&out[3], (int32_t)gridDim.x);
+      store_system(&out[4], a.ctrl->stale.v);
+    }
   }
 }
 
@@ -750,6 +821,7 @@ __global__ __launch_bounds__(kBlock) void k_persistent(KArgs a, int max_rounds) 
     const int more = __hip_atomic_load(&a.ctrl->more[r % 3].v, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
     if (!more) break;  // grid-uniform: read after a barrier, written before it
+    if (blockIdx.x == 0) fold_trace(a);
     phase<RP, S, L, kSpec>(a, r, blockIdx.x, gridDim.x, sm);
     if (!grid_barrier(a.ctrl, epoch)) return;
     phase<RP, S, L, kDetect>(a, r, blockIdx.x, gridDim.x, sm);
@@ -761,25 +833,37 @@ __global__ __launch_bounds__(kBlock) void k_persistent(KArgs a, int max_rounds) 
 
 // Degree classes: medium (light_max < deg < heavy_min) and heavy
 // (deg >= heavy_min) vertex lists; counts[2] receives the maximum degree.
+// With low1 given (rows ascending), bit v of low1 records whether v's first
+// neighbour is below v: the round-1 outcome, which depends on the graph only.
+// A wavefront covers 64 consecutive vertices per step, so its ballot is one
+// whole bitmap word.
 template <typename RP>
-__global__ void k_classify(const RP* rowptr, int32_t n, int32_t light_max, int32_t heavy_min,
-                           int32_t* mlist, int32_t* hlist, int32_t* counts, int32_t* widx) {
+__global__ void k_classify(const RP* rowptr, const int32_t* colidx, int32_t n, int32_t light_max,
+                           int32_t heavy_min, int32_t* mlist, int32_t* hlist, int32_t* counts,
+                           int32_t* widx, uint64_t* low1) {
   __shared__ int sh_max;
   if (threadIdx.x == 0) sh_max = 0;
   __syncthreads();
   int mx = 0;
-  const long tid = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  const long nth = (long)gridDim.x * blockDim.x;
-  for (long v = tid; v < n; v += nth) {
-    RP d = rowptr[v + 1] - rowptr[v];
-    int di = d > (RP)INT_MAX ? INT_MAX : (int)d;
-    mx = di > mx ? di : mx;
-    int w = -1;  // wide block: medium i -> i; heavy j -> mcount + j (set afterwards)
-    if (di > light_max) {
-      if (di >= heavy_min) hlist[atomicAdd(&counts[1], 1)] = (int)v;
-      else mlist[w = atomicAdd(&counts[0], 1)] = (int)v;
+  const long nth = (long)gridDim.x * blockDim.x;  // a multiple of 64
+  for (long v0 = blockIdx.x * (long)blockDim.x + (threadIdx.x & ~(kWave - 1)); v0 < n; v0 += nth) {
+    const long v = v0 + lane_id();
+    bool low = false;
+    if (v < n) {
+      const RP b = rowptr[v], e = rowptr[v + 1];
+      const RP d = e - b;
+      int di = d > (RP)INT_MAX ? INT_MAX : (int)d;
+      mx = di > mx ? di : mx;
+      int w = -1;  // wide block: medium i -> i; heavy j -> mcount + j (set afterwards)
+      if (di > light_max) {
+        if (di >= heavy_min) hlist[atomicAdd(&counts[1], 1)] = (int)v;
+        else mlist[w = atomicAdd(&counts[0], 1)] = (int)v;
+      }
+      widx[v] = w;
+      low = low1 && e > b && colidx[b] < v;
     }
-    widx[v] = w;
+    const uint64_t word = __ballot(low);
+    if (low1 && lane_id() == 0) low1[v0 / kWave] = word;
   }
   atomicMax(&sh_max, mx);
   __syncthreads();
@@ -958,26 +1042,31 @@ int launch_advance_base(const KArgs& a, int by, void* stream) {
   return (int)hipGetLastError();
 }
 
-int launch_finish(const KArgs& a, int sbytes, int grid, void* stream) {
+int launch_finish(const KArgs& a, int sbytes, int32_t* out, void* stream) {
   hipStream_t s = (hipStream_t)stream;
+  // about 16 vertices per thread, at most kFinishBlocks workgroups
+  const long per = 16l * kBlock;
+  const int grid = (int)std::max<long>(1, std::min<long>(kFinishBlocks, ((long)a.n + per - 1) / per));
   switch (sbytes) {
-    case 1: hipLaunchKernelGGL(k_finish<int8_t>, dim3(grid), dim3(kBlock), 0, s, a); break;
-    case 2: hipLaunchKernelGGL(k_finish<int16_t>, dim3(grid), dim3(kBlock), 0, s, a); break;
-    case 4: hipLaunchKernelGGL(k_finish<int32_t>, dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 1: hipLaunchKernelGGL(k_finish<int8_t>, dim3(grid), dim3(kBlock), 0, s, a, out); break;
+    case 2: hipLaunchKernelGGL(k_finish<int16_t>, dim3(grid), dim3(kBlock), 0, s, a, out); break;
+    case 4: hipLaunchKernelGGL(k_finish<int32_t>, dim3(grid), dim3(kBlock), 0, s, a, out); break;
     default: return (int)hipErrorInvalidValue;
   }
   return (int)hipGetLastError();
 }
 
-int launch_classify(const void* rowptr, bool rp64, int32_t n, int32_t light_max, int32_t heavy_min,
-                    int32_t* mlist, int32_t* hlist, int32_t* counts, int32_t* widx, int grid,
-                    void* stream) {
+int launch_classify(const void* rowptr, bool rp64, const int32_t* colidx, int32_t n,
+                    int32_t light_max, int32_t heavy_min, int32_t* mlist, int32_t* hlist,
+                    int32_t* counts, int32_t* widx, uint64_t* low1, int grid, void* stream) {
   if (rp64)
     hipLaunchKernelGGL(k_classify<int64_t>, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream,
-                       (const int64_t*)rowptr, n, light_max, heavy_min, mlist, hlist, counts, widx);
+                       (const int64_t*)rowptr, colidx, n, light_max, heavy_min, mlist, hlist,
+                       counts, widx, low1);
   else
     hipLaunchKernelGGL(k_classify<int32_t>, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream,
-                       (const int32_t*)rowptr, n, light_max, heavy_min, mlist, hlist, counts, widx);
+                       (const int32_t*)rowptr, colidx, n, light_max, heavy_min, mlist, hlist,
+                       counts, widx, low1);
   return (int)hipGetLastError();
 }
 
