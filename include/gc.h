@@ -91,10 +91,8 @@ enum gc_flags {
  *
  * The graph arrays are BORROWED: they must stay allocated and unchanged
  * until gc_destroy.  The library allocates O(n) device scratch (the state
- * array of 1/2/4 bytes per vertex, a 4-byte resume offset per vertex, one
- * bit per vertex recording the round-1 outcome of ascending rows (computed
- * here, from the graph alone), worklists and counters; on the first
- * push-algorithm call 32 flag bytes per
+ * array of 1/2/4 bytes per vertex, a 4-byte resume offset per vertex,
+ * worklists and counters; on the first push-algorithm call 32 flag bytes per
  * vertex plus 480 per vertex handled by a whole wave or workgroup, see
  * GC_OPT_MEDIUM_DEGREE) and a small pinned host block; it synchronises
  * `stream` before returning.  The handle belongs to the device current at
@@ -130,12 +128,8 @@ int gc_color(gc_handle h, int32_t *colors_out, void *stream);
  * (0 when n = 0), `num_colors` max colour + 1 (0 when n = 0).  Either
  * pointer may be NULL.  Returns GC_EROUNDS if the call stopped at the round
  * cap (GC_OPT_MAX_ROUNDS) with vertices still uncoloured, GC_EINVAL if
- * vertices were left uncoloured otherwise or a vertex kept colour 0 in
- * round 1 although its row now has a lower neighbour (both mean the graph
- * arrays were changed after gc_create, against the contract; the handle
- * then rebuilds its per-graph data on the next gc_color), GC_EDEVICE on a
- * device error.  These checks are a courtesy: other changes to the graph
- * give undefined results.
+ * vertices were left uncoloured otherwise (the graph arrays were changed
+ * after gc_create, against the contract), GC_EDEVICE on a device error.
  */
 int gc_get_stats(gc_handle h, int64_t *rounds, int32_t *num_colors);
 

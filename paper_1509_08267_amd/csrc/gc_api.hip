@@ -43,8 +43,7 @@ struct Pinned {  // read-back area in pinned host memory
   int32_t ncolors;
   int32_t abort;
   int32_t left;
-  int32_t stale;
-  int32_t pad1[2];
+  int32_t pad1[3];
   int32_t fin[gc::kFinishWords];  // written by the finishing kernel (layout at launch_finish)
 };
 
@@ -95,7 +94,6 @@ struct gc_ctx {
   int64_t wide_blocks = 0;    // blocks allocated in `wide`
   int32_t* widx = nullptr;    // device, n: wide block of each medium/heavy vertex, -1 otherwise
   int32_t* skip = nullptr;    // device, n: final-prefix offset of each row (sorted rows)
-  uint64_t* low1 = nullptr;   // device, ceil(n / 64) words: round-1 losers (sorted rows)
   int32_t* part = nullptr;    // device, cus * kMaxBlocksPerCu: per-workgroup round sizes
   int epoch = 0;              // epoch of the last call's pushed flags (1..255)
   Pinned* host = nullptr;     // pinned
@@ -224,7 +222,6 @@ static KArgs make_args(const gc_ctx* h, int32_t* colors, int light_max) {
   a.wide = h->wide;
   a.widx = h->widx;
   a.skip = h->skip;
-  a.low1 = h->low1;
   a.part = h->part;
   a.ctrl = h->ctrl;
   return a;
@@ -250,10 +247,8 @@ static int classify(gc_ctx* h, hipStream_t s) {
   const int light = light_max_of(h, L);
   const int heavy = std::max(h->heavy_min, light + 1);
   HIPCHECK(h, hipMemsetAsync(h->dcounts, 0, 3 * sizeof(int32_t), s));
-  const bool sorted = (h->flags & GC_ROWS_SORTED) != 0;
-  LCHECK(h, gc::launch_classify(h->rowptr, h->rp64, h->colidx, (int32_t)h->n, light, heavy,
-                                h->mlist, h->hlist, h->dcounts, h->widx,
-                                sorted ? h->low1 : nullptr, grid_of(h), s));
+  LCHECK(h, gc::launch_classify(h->rowptr, h->rp64, (int32_t)h->n, light, heavy, h->mlist, h->hlist,
+                                h->dcounts, h->widx, grid_of(h), s));
   HIPCHECK(h, hipMemcpyAsync(h->host->counts, h->dcounts, 3 * sizeof(int32_t),
                              hipMemcpyDeviceToHost, s));
   HIPCHECK(h, hipStreamSynchronize(s));
@@ -289,7 +284,6 @@ static void free_ctx(gc_ctx* h) {
   if (h->wide) (void)hipFree(h->wide);
   if (h->widx) (void)hipFree(h->widx);
   if (h->skip) (void)hipFree(h->skip);
-  if (h->low1) (void)hipFree(h->low1);
   if (h->part) (void)hipFree(h->part);
   if (h->o_rowptr) (void)hipFree(h->o_rowptr);
   if (h->o_colidx) (void)hipFree(h->o_colidx);
@@ -344,7 +338,6 @@ extern "C" int gc_create(gc_handle* out, const void* rowptr, const int32_t* coli
   CREATE_CHECK(hipMalloc((void**)&h->dcounts, 8 * sizeof(int32_t)));
   CREATE_CHECK(hipMalloc((void**)&h->widx, (size_t)std::max<int64_t>(n, 1) * sizeof(int32_t)));
   CREATE_CHECK(hipMalloc((void**)&h->skip, (size_t)std::max<int64_t>(n, 1) * sizeof(int32_t)));
-  CREATE_CHECK(hipMalloc((void**)&h->low1, (size_t)std::max<int64_t>((n + 63) / 64, 1) * 8));
   CREATE_CHECK(hipMalloc((void**)&h->part, (size_t)h->cus * gc::kMaxBlocksPerCu * sizeof(int32_t)));
   CREATE_CHECK(hipHostMalloc((void**)&h->host, sizeof(Pinned), hipHostMallocDefault));
   CREATE_CHECK(hipHostGetDevicePointer((void**)&h->fin_dev, h->host->fin, 0));
@@ -454,7 +447,7 @@ static bool usable(const Captured& c, int K, int L, int grid, const KArgs& a) {
          b.mlist == a.mlist && b.mcount == a.mcount && b.hlist == a.hlist &&
          b.hcount == a.hcount && b.sorted == a.sorted && b.push == a.push && b.seq == a.seq &&
          b.seen == a.seen && b.wide == a.wide && b.widx == a.widx && b.skip == a.skip &&
-         b.low1 == a.low1 && b.part == a.part && b.ctrl == a.ctrl;
+         b.part == a.part && b.ctrl == a.ctrl;
 }
 
 static float elapsed(hipEvent_t a, hipEvent_t b) {
@@ -760,7 +753,6 @@ static void fold_finish(gc_ctx* h) {
   const int32_t* f = p->fin;
   p->last_round = f[0];
   p->abort = f[1];
-  p->stale = f[4];
   const int g = std::min(std::max(f[3], 0), gc::kFinishBlocks);
   int32_t nc = 0;
   int64_t left = f[2];
@@ -781,12 +773,6 @@ static int wait_done(gc_ctx* h) {
   fold_finish(h);  // the call has completed (also when another path waited for it)
   collect_profile(h);
   if (h->host->abort) return set_err(h, GC_EDEVICE, "persistent kernel: grid barrier timed out");
-  if (h->host->stale) {  // the set-up data (degree classes, round-1 bitmap) is rebuilt next call
-    h->lists_dirty = true;
-    h->known_rounds = 0;
-    return set_err(h, GC_EINVAL, "a vertex coloured in round 1 has a lower neighbour: the graph "
-                   "changed after gc_create");
-  }
   if (h->host->left) {
     if (h->max_rounds > 0 && h->host->last_round >= h->max_rounds)
       return set_err(h, GC_EROUNDS, "round cap reached with %d vertices uncoloured", h->host->left);

@@ -29,7 +29,7 @@ constexpr int kPushColors = 32;     // colours tracked per vertex by pushed flag
 constexpr int kWideColors = 480;    // further colours (32..511) tracked for medium/heavy vertices
 constexpr int kMaxBlocksPerCu = 64; // workgroups per CU of any round kernel (option limit)
 constexpr int kFinishBlocks = 512;  // most workgroups of the finishing pass (one stats pair each)
-constexpr int kFinishHeader = 8;   // its leading output words (see launch_finish)
+constexpr int kFinishHeader = 4;   // its leading output words (see launch_finish)
 constexpr int kFinishWords = kFinishHeader + 2 * kFinishBlocks;
 
 // One 128-byte line per field that different blocks write, so that flags and
@@ -43,7 +43,6 @@ struct Ctrl {
   Line more[3];          // slot r % 3 == 1 when round r has uncoloured vertices
   Line last_round;       // last round that had uncoloured vertices
   Line round_base;       // first round of the next captured chunk
-  Line stale;            // set when round 1 finds a row that differs from the set-up bitmap
   Line bar;              // grid barrier arrivals (monotonic within a launch)
   Line abort;            // set when a barrier wait exceeded its spin limit
   Line left;             // vertices still uncoloured after the last round
@@ -78,10 +77,6 @@ struct KArgs {
   const int32_t* widx;    // n: index of v's wide flag block, -1 for light vertices
   int32_t* skip;          // n: lower neighbours before this offset of v's row are final
                           // (sorted rows); zeroed by round 1
-  const uint64_t* low1;   // ceil(n / 64) words: bit v set when v's first neighbour is below v,
-                          // i.e. v loses round 1 (sorted rows; built by the classify pass).
-                          // Round 1 checks each winner's first entry against it and sets
-                          // ctrl->stale on a mismatch (a graph changed after set-up)
   int32_t* part;          // cus * kMaxBlocksPerCu: active vertices of each workgroup of the
                           // last detect pass; the next pass folds them into ctrl->trace
   Ctrl* ctrl;
@@ -132,21 +127,17 @@ int launch_advance_base(const KArgs& a, int by, void* stream);
 // The state becomes the caller's int32 colours.  `out` (kFinishWords words of
 // device-visible pinned host memory) receives, by system-scope stores:
 //   out[0] last round, out[1] abort flag, out[2] uncoloured count recorded by
-//   earlier passes (ctrl->left), out[3] workgroups G of this pass, out[4] the
-//   stale-graph flag (ctrl->stale), out[5..7] unused, and for each workgroup
-//   b < G: out[8 + 2b] = its largest colour + 1 (0 if none), out[9 + 2b] = its
-//   uncoloured vertices.
+//   earlier passes (ctrl->left), out[3] workgroups G of this pass, and for
+//   each workgroup b < G: out[4 + 2b] = its largest colour + 1 (0 if none),
+//   out[5 + 2b] = its uncoloured vertices.
 // The host folds them once the stream has passed this kernel.
 int launch_finish(const KArgs& a, int sbytes, int32_t* out, void* stream);
 int launch_persistent(const KArgs& a, bool rp64, int sbytes, int lanes, int max_rounds, int grid,
                       void* stream);
 int persistent_max_grid(bool rp64, int sbytes, int lanes, int* grid_out);
-// Degree classes; with `low1` non-null (rows ascending) also the round-1
-// losers' bitmap from each row's first entry.
-int launch_classify(const void* rowptr, bool rp64, const int32_t* colidx, int32_t n,
-                    int32_t light_max, int32_t heavy_min, int32_t* mlist, int32_t* hlist,
-                    int32_t* counts /*[3]: medium, heavy, maxdeg*/, int32_t* widx, uint64_t* low1,
-                    int grid, void* stream);
+int launch_classify(const void* rowptr, bool rp64, int32_t n, int32_t light_max, int32_t heavy_min,
+                    int32_t* mlist, int32_t* hlist, int32_t* counts /*[3]: medium, heavy, maxdeg*/,
+                    int32_t* widx, int grid, void* stream);
 int launch_wide_index(const int32_t* hlist, int32_t hcount, int32_t mcount, int32_t* widx,
                       void* stream);
 int launch_validate(const void* rowptr, bool rp64, const int32_t* colidx, int32_t n, int64_t m,

@@ -587,13 +587,8 @@ __global__ __launch_bounds__(kBlock) void k_phase(KArgs a, int round, int from_b
 
 // Round 1 in closed form for sorted rows: nothing is final, so every vertex
 // tries colour 0 and v keeps it exactly when no neighbour has a lower id,
-// i.e. when its first (smallest) neighbour is above v.  That outcome is a
-// property of the graph, recorded once per graph in the low1 bitmap, so the
-// pass reads one bit per vertex instead of a row sector.  A winner checks
-// the first entry of its own row (a few percent of the vertices) and flags a
-// graph changed since the bitmap was built; a stale loser bit only delays a
-// vertex.  One lane per vertex writes the whole state array, so no
-// initialisation pass is needed.
+// i.e. when its first (smallest) neighbour is above v.  One lane per vertex
+// writes the whole state array, so no initialisation pass is needed.
 template <typename RP, typename S>
 __global__ __launch_bounds__(kBlock) void k_round1_sorted(KArgs a) {
   __shared__ HeavySmem sm;
@@ -603,11 +598,8 @@ __global__ __launch_bounds__(kBlock) void k_round1_sorted(KArgs a) {
   const long tid = blockIdx.x * (long)blockDim.x + threadIdx.x;
   const long nth = (long)gridDim.x * blockDim.x;
   for (long v = tid; v < a.n; v += nth) {
-    const bool lose = (a.low1[v / kWave] >> (v % kWave)) & 1;
-    if (!lose) {
-      const RP b = rp[v];
-      if (rp[v + 1] > b && a.colidx[b] < v) a.ctrl->stale.v = 1;
-    }
+    const RP b = rp[v], e = rp[v + 1];
+    const bool lose = e > b && a.colidx[b] < v;
     st[v] = lose ? (S)-1 : (S)0;
     a.skip[v] = 0;
     tl.lost += lose;
@@ -638,15 +630,15 @@ __global__ __launch_bounds__(kBlock) void k_round1_sorted_push(KArgs a) {
     RP pb = 0;
     int len = 0;
     if (v < a.n) {
-      const bool lose = (a.low1[ch] >> lane_id()) & 1;
+      const RP b = rp[v], e = rp[v + 1];
+      const bool lose = e > b && a.colidx[b] < v;
       st[v] = lose ? (S)-1 : (S)0;
       a.skip[v] = 0;
       tl.lost += lose;
       tl.active += 1;
       if (!lose) {
-        pb = rp[v];
-        len = (int)(rp[v + 1] - pb);
-        if (len > 0 && a.colidx[pb] < v) a.ctrl->stale.v = 1;
+        pb = b;
+        len = (int)(e - b);
       }
     }
     push_flat<RP, S, false>(a, st, pb, len, 0, epoch);
@@ -686,7 +678,6 @@ __global__ void k_init(KArgs a) {
     a.ctrl->more[2].v = 0;
     a.ctrl->last_round.v = 0;
     a.ctrl->round_base.v = 2;
-    a.ctrl->stale.v = 0;
     a.ctrl->pend.v = 0;
     a.ctrl->bar.v = 0;
     a.ctrl->abort.v = 0;
@@ -756,7 +747,6 @@ __global__ __launch_bounds__(kBlock) void k_finish(KArgs a, int32_t* out) {
       store_system(&out[1], a.ctrl->abort.v);
       store_system(&out[2], a.ctrl->left.v);
       store_system(&out[3], (int32_t)gridDim.x);
-      store_system(&out[4], a.ctrl->stale.v);
     }
   }
 }
@@ -833,37 +823,25 @@ __global__ __launch_bounds__(kBlock) void k_persistent(KArgs a, int max_rounds) 
 
 // Degree classes: medium (light_max < deg < heavy_min) and heavy
 // (deg >= heavy_min) vertex lists; counts[2] receives the maximum degree.
-// With low1 given (rows ascending), bit v of low1 records whether v's first
-// neighbour is below v: the round-1 outcome, which depends on the graph only.
-// A wavefront covers 64 consecutive vertices per step, so its ballot is one
-// whole bitmap word.
 template <typename RP>
-__global__ void k_classify(const RP* rowptr, const int32_t* colidx, int32_t n, int32_t light_max,
-                           int32_t heavy_min, int32_t* mlist, int32_t* hlist, int32_t* counts,
-                           int32_t* widx, uint64_t* low1) {
+__global__ void k_classify(const RP* rowptr, int32_t n, int32_t light_max, int32_t heavy_min,
+                           int32_t* mlist, int32_t* hlist, int32_t* counts, int32_t* widx) {
   __shared__ int sh_max;
   if (threadIdx.x == 0) sh_max = 0;
   __syncthreads();
   int mx = 0;
-  const long nth = (long)gridDim.x * blockDim.x;  // a multiple of 64
-  for (long v0 = blockIdx.x * (long)blockDim.x + (threadIdx.x & ~(kWave - 1)); v0 < n; v0 += nth) {
-    const long v = v0 + lane_id();
-    bool low = false;
-    if (v < n) {
-      const RP b = rowptr[v], e = rowptr[v + 1];
-      const RP d = e - b;
-      int di = d > (RP)INT_MAX ? INT_MAX : (int)d;
-      mx = di > mx ? di : mx;
-      int w = -1;  // wide block: medium i -> i; heavy j -> mcount + j (set afterwards)
-      if (di > light_max) {
-        if (di >= heavy_min) hlist[atomicAdd(&counts[1], 1)] = (int)v;
-        else mlist[w = atomicAdd(&counts[0], 1)] = (int)v;
-      }
-      widx[v] = w;
-      low = low1 && e > b && colidx[b] < v;
+  const long tid = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const long nth = (long)gridDim.x * blockDim.x;
+  for (long v = tid; v < n; v += nth) {
+    RP d = rowptr[v + 1] - rowptr[v];
+    int di = d > (RP)INT_MAX ? INT_MAX : (int)d;
+    mx = di > mx ? di : mx;
+    int w = -1;  // wide block: medium i -> i; heavy j -> mcount + j (set afterwards)
+    if (di > light_max) {
+      if (di >= heavy_min) hlist[atomicAdd(&counts[1], 1)] = (int)v;
+      else mlist[w = atomicAdd(&counts[0], 1)] = (int)v;
     }
-    const uint64_t word = __ballot(low);
-    if (low1 && lane_id() == 0) low1[v0 / kWave] = word;
+    widx[v] = w;
   }
   atomicMax(&sh_max, mx);
   __syncthreads();
@@ -1056,17 +1034,15 @@ int launch_finish(const KArgs& a, int sbytes, int32_t* out, void* stream) {
   return (int)hipGetLastError();
 }
 
-int launch_classify(const void* rowptr, bool rp64, const int32_t* colidx, int32_t n,
-                    int32_t light_max, int32_t heavy_min, int32_t* mlist, int32_t* hlist,
-                    int32_t* counts, int32_t* widx, uint64_t* low1, int grid, void* stream) {
+int launch_classify(const void* rowptr, bool rp64, int32_t n, int32_t light_max, int32_t heavy_min,
+                    int32_t* mlist, int32_t* hlist, int32_t* counts, int32_t* widx, int grid,
+                    void* stream) {
   if (rp64)
     hipLaunchKernelGGL(k_classify<int64_t>, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream,
-                       (const int64_t*)rowptr, colidx, n, light_max, heavy_min, mlist, hlist,
-                       counts, widx, low1);
+                       (const int64_t*)rowptr, n, light_max, heavy_min, mlist, hlist, counts, widx);
   else
     hipLaunchKernelGGL(k_classify<int32_t>, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream,
-                       (const int32_t*)rowptr, colidx, n, light_max, heavy_min, mlist, hlist,
-                       counts, widx, low1);
+                       (const int32_t*)rowptr, n, light_max, heavy_min, mlist, hlist, counts, widx);
   return (int)hipGetLastError();
 }
 
