@@ -222,6 +222,48 @@ __device__ __forceinline__ bool detect_wave4_skip(const int32_t* __restrict__ co
   return false;
 }
 
+// detect_wave4_skip's scan by a group of GL lanes (lanes gbase ..
+// gbase + GL - 1, mask gmask; GL a power of two up to 64) for one vertex:
+// each step covers 4 * GL entries as four sub-ranges of GL, visited in order.
+// Used where a chunk holds few uncoloured vertices, so that a long lower
+// prefix is not walked four entries at a time by a single lane.
+template <typename RP, typename S>
+__device__ __forceinline__ bool detect_group4_skip(const int32_t* __restrict__ colidx,
+                                                   const S* __restrict__ st, RP b, RP e, int v,
+                                                   int t, int GL, int gl, uint64_t gmask,
+                                                   int gbase, int* skip) {
+  int first = -1;
+  for (RP kb = b + *skip; kb < e; kb += 4 * GL) {  // group-uniform
+    int u[4], s[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const RP k = kb + j * GL + gl;
+      u[j] = k < e ? colidx[k] : INT32_MAX;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) s[j] = u[j] < v ? (int)st[u[j]] : 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const bool low = u[j] < v;
+      const uint64_t am = (__ballot(low && s[j] < 0) & gmask) >> gbase;
+      const uint64_t cm = (__ballot(low && tent_of(s[j]) == t) & gmask) >> gbase;
+      const uint64_t pm = (__ballot(!low) & gmask) >> gbase;
+      const int base = (int)(kb - b) + j * GL;
+      if (first < 0 && am) first = base + __builtin_ctzll(am);
+      if (cm) {
+        *skip = first >= 0 ? first : base + __builtin_ctzll(cm);
+        return true;
+      }
+      if (pm) {
+        *skip = first >= 0 ? first : base + __builtin_ctzll(pm);
+        return false;
+      }
+    }
+  }
+  *skip = first >= 0 ? first : (int)(e - b);
+  return false;
+}
+
 // Conflict scan with a resume offset (sorted rows), by one lane for its own
 // vertex: starting at b + *skip, does a lower-id neighbour of v that is still
 // uncoloured carry tentative colour t?  The scan stops at the first conflict

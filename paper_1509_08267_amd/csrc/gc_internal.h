@@ -27,6 +27,8 @@ constexpr int kTraceRounds = 65536; // rounds whose |U_r| is recorded
 constexpr int kHeavyWindow = 4096;  // LDS colour window of the block-per-vertex path (bits)
 constexpr int kPushColors = 32;     // colours tracked per vertex by pushed flags
 constexpr int kWideColors = 480;    // further colours (32..511) tracked for medium/heavy vertices
+constexpr int kSparseChunk = 32;    // detect: at most this many uncoloured vertices in a chunk
+                                    // -> a group of lanes each (at least 2)
 constexpr int kMaxBlocksPerCu = 64; // workgroups per CU of any round kernel (option limit)
 constexpr int kFinishBlocks = 512;  // most workgroups of the finishing pass (one stats pair each)
 constexpr int kFinishHeader = 4;   // its leading output words (see launch_finish)

@@ -246,11 +246,45 @@ __device__ void light_phase(const KArgs& a, long wave_gid, long nwaves, Tally& t
     if (am == 0) continue;
     if (PHASE == kDetect && sorted) {
       // sorted rows: each lane scans for its own vertex (most scans stop
-      // within a few entries), then the chunk's winners push together
+      // within a few entries), then the chunk's winners push together.  A
+      // chunk with at most kSparseChunk uncoloured vertices (the later rounds)
+      // gives each of them a group of 64 / 2^ceil(log2 count) lanes instead.
       const int t = ~s;
       RP pb = 0;
       int len = 0;
-      if (act) {
+      const int cnt = __popcll(am);
+      if (cnt <= kSparseChunk) {  // wave-uniform
+        const int GL = kWave >> (cnt <= 1 ? 0 : 32 - __builtin_clz((unsigned)cnt - 1));
+        const int g = lane / GL;
+        const bool valid = g < cnt;
+        const int pos = nth_set_bit(am, valid ? g : 0);
+        const RP vb = shfl_any<RP>(b, pos);
+        const RP ve = shfl_any<RP>(e, pos);
+        const int vt = __shfl(t, pos);
+        const int vv = (int)(ch * kWave) + pos;
+        int sk = 0, lose = 0;
+        if (valid) {  // group-uniform
+          const int sk0 = a.skip[vv];
+          sk = sk0;
+          const uint64_t gmask = GL == kWave ? ~0ull : ((1ull << GL) - 1) << (g * GL);
+          lose = detect_group4_skip<RP, S>(a.colidx, st, vb, ve, vv, vt, GL, lane % GL, gmask,
+                                           g * GL, &sk);
+          if (lane % GL == 0 && sk != sk0) a.skip[vv] = sk;
+        }
+        // back to the owning lanes: the vertex of lane v is the rank-th active one
+        const int src = act ? __popcll(am & ((1ull << lane) - 1)) * GL : 0;
+        const int osk = __shfl(sk, src);
+        const int olose = __shfl(lose, src);
+        if (act) {
+          if (!olose) {
+            st[v] = (S)t;
+            pb = b + osk;
+            len = (int)(e - pb);
+          }
+          tl.lost += olose;
+          tl.active += 1;
+        }
+      } else if (act) {
         const int sk0 = a.skip[v];
         int sk = sk0;
         const bool lose = detect_lane_skip<RP, S>(a.colidx, st, b, e, v, t, &sk);
