@@ -110,7 +110,7 @@ struct GraphRun {
 // vertices by the whole workgroup: each wavefront walks 64-vertex chunks,
 // ballots the uncoloured ones and hands them to its groups of L lanes.
 template <typename S, int L, bool SPEC>
-__device__ bool graph_pass(const GraphRun& g, S* st) {
+__device__ __forceinline__ bool graph_pass(const GraphRun& g, S* st) {
   const int lane = lane_id();
   const int gl = lane & (L - 1);
   const int grp = lane / L;
@@ -162,7 +162,7 @@ __device__ bool graph_pass(const GraphRun& g, S* st) {
 // Rounds of one graph until done or max_rounds more rounds have run.
 // Returns the rounds completed; *left receives the vertices still uncoloured.
 template <typename S, int L, bool IN_LDS>
-__device__ int run_graph(const GraphRun& g, S* st, int* left) {
+__device__ __forceinline__ int run_graph(const GraphRun& g, S* st, int* left) {
   __shared__ int sh_cnt;
   bool any = false;
   int r = g.rounds_in;
@@ -207,7 +207,7 @@ __device__ int run_graph(const GraphRun& g, S* st, int* left) {
 }
 
 template <int L>
-__device__ int dispatch_state(const GraphRun& g, int maxdeg, char* smem, int* left) {
+__device__ __forceinline__ int dispatch_state(const GraphRun& g, int maxdeg, char* smem, int* left) {
   if (maxdeg <= 127 && g.n <= kBatchLds) return run_graph<int8_t, L, true>(g, (int8_t*)smem, left);
   if (maxdeg <= 32767 && 2 * g.n <= kBatchLds)
     return run_graph<int16_t, L, true>(g, (int16_t*)smem, left);
@@ -215,7 +215,7 @@ __device__ int dispatch_state(const GraphRun& g, int maxdeg, char* smem, int* le
   return run_graph<int32_t, L, false>(g, g.out, left);
 }
 
-__global__ __launch_bounds__(kBatchBlock) void k_batch_color(int64_t G, gc_graph_desc* d,
+__global__ __launch_bounds__(kBatchBlock, 8) void k_batch_color(int64_t G, gc_graph_desc* d,
                                                             const int32_t* rowptr_base,
                                                             const int32_t* colidx_base,
                                                             int32_t* colors_base, int max_rounds,
