@@ -217,6 +217,7 @@ static KArgs make_args(const gc_ctx* h, int32_t* colors, int light_max) {
   a.push = use_push(h) ? 1 : 0;
   a.seq = use_seq(h) ? 1 : 0;
   a.seen = h->seen;
+  a.flags_by_chunk = (h->mcount + h->hcount == 0) ? 1 : 0;
   a.epoch = h->epoch;
   a.clear_seen = h->epoch == 1;
   a.wide = h->wide;
@@ -446,7 +447,7 @@ static bool usable(const Captured& c, int K, int L, int grid, const KArgs& a) {
          b.colidx == a.colidx && b.st == a.st && b.n == a.n && b.light_max == a.light_max &&
          b.mlist == a.mlist && b.mcount == a.mcount && b.hlist == a.hlist &&
          b.hcount == a.hcount && b.sorted == a.sorted && b.push == a.push && b.seq == a.seq &&
-         b.seen == a.seen && b.wide == a.wide && b.widx == a.widx && b.skip == a.skip &&
+         b.seen == a.seen && b.flags_by_chunk == a.flags_by_chunk && b.wide == a.wide && b.widx == a.widx && b.skip == a.skip &&
          b.part == a.part && b.ctrl == a.ctrl;
 }
 
@@ -636,7 +637,8 @@ extern "C" int gc_color(gc_handle h, int32_t* colors_out, void* stream) {
   if (h->algorithm == GC_ALGO_BLOCKS) return color_blocks(h, colors_out, user_out, s);
   if (use_push(h)) {
     if (!h->seen && h->n > 0) {
-      hipError_t e = hipMalloc((void**)&h->seen, (size_t)h->n * gc::kPushColors);
+      const size_t nv = (size_t)(h->n + gc::kWave - 1) / gc::kWave * gc::kWave;  // whole chunks
+      hipError_t e = hipMalloc((void**)&h->seen, nv * gc::kPushColors);
       if (e != hipSuccess) return set_err(h, GC_ENOMEM, "colour flags: %s", hipGetErrorString(e));
       h->epoch = 0;
     }

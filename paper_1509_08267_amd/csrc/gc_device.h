@@ -91,6 +91,21 @@ __device__ __forceinline__ int spec_group(const int32_t* __restrict__ colidx,
   }
 }
 
+// Position of v's flag for colour c (< kPushColors) in KArgs::seen.  By
+// vertex: v's 32 bytes are consecutive.  By chunk: a 64-vertex chunk's 2 KB
+// are 32 rows of 64 bytes, row c holding colour c of every vertex of the
+// chunk, so a wavefront reads one colour of its whole chunk with one
+// coalesced load, a speculate pass reads only the rows up to the largest
+// colour its chunk needs (the by-vertex block costs a whole 32-byte sector
+// per vertex), and the pushes of one colour to a chunk meet in one row.  The
+// by-chunk layout is used only without medium and heavy vertices, whose
+// passes read one vertex's 32 flags on their own.
+__device__ __forceinline__ size_t flag_index(const KArgs& a, int v, int c) {
+  return a.flags_by_chunk
+             ? ((size_t)(v / kWave) * kPushColors + c) * kWave + (size_t)(v % kWave)
+             : (size_t)v * kPushColors + c;
+}
+
 // A vertex that has just committed colour t marks t as taken for its
 // neighbours (row [b, e)) that are still uncoloured: byte t of the
 // neighbour's flag block gets the call's epoch (t < 32), or byte t - 32 of
@@ -114,11 +129,11 @@ __device__ __forceinline__ void push_colour(const KArgs& a, const S* __restrict_
       for (int j = 0; j < 4; ++j) s[j] = st[u[j]];
 #pragma unroll
       for (int j = 0; j < 4; ++j)
-        if (s[j] < 0) a.seen[(size_t)u[j] * kPushColors + t] = (uint8_t)epoch;
+        if (s[j] < 0) a.seen[flag_index(a, u[j], t)] = (uint8_t)epoch;
     }
     for (; k < e; k += step) {
       const int u = a.colidx[k];
-      if (st[u] < 0) a.seen[(size_t)u * kPushColors + t] = (uint8_t)epoch;
+      if (st[u] < 0) a.seen[flag_index(a, u, t)] = (uint8_t)epoch;
     }
   } else if (t < kPushColors + kWideColors) {
     // the same with the neighbour's wide-block index gathered beside its
@@ -168,7 +183,8 @@ __device__ __forceinline__ int first_free_wide(const uint8_t* wide, int w, int e
 }
 
 // Bit c of the result is set when byte c of v's flag block equals epoch
-// (a neighbour of v has final colour c), for c < kPushColors = 32.
+// (a neighbour of v has final colour c), for c < kPushColors = 32.  The
+// by-vertex flag layout.
 __device__ __forceinline__ uint32_t taken_colours(const uint8_t* seen, int v, int epoch) {
   const uint4* p = (const uint4*)(seen + (size_t)v * kPushColors);
   const uint4 x = p[0], y = p[1];
@@ -351,7 +367,7 @@ __device__ __forceinline__ void push_flat(const KArgs& a, const S* __restrict__ 
     for (int q = 0; q < 4; ++q) {
       if (!ok[q] || s[q] >= 0) continue;
       if (tt[q] < kPushColors) {
-        a.seen[(size_t)u[q] * kPushColors + tt[q]] = (uint8_t)epoch;
+        a.seen[flag_index(a, u[q], tt[q])] = (uint8_t)epoch;
       } else if (tt[q] < kPushColors + kWideColors) {
         const int w = a.widx[u[q]];
         if (w >= 0) a.wide[(size_t)w * kWideColors + (tt[q] - kPushColors)] = (uint8_t)epoch;

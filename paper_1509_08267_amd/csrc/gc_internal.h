@@ -71,8 +71,11 @@ struct KArgs {
   int32_t push;           // forbidden colours pushed by committing neighbours
   int32_t seq;            // id-priority First Fit: speculate picks the vertices whose lower
                           // neighbours are all final, detect commits them (no conflicts)
-  uint8_t* seen;          // n * kPushColors: byte c of v == epoch when a neighbour of v
-                          // has final colour c (plain byte stores, no atomics)
+  uint8_t* seen;          // ceil(n / 64) * 64 * kPushColors: byte c of v == epoch when a
+                          // neighbour of v has final colour c (plain byte stores, no atomics);
+                          // at flag_index(v, c) (gc_device.h)
+  int32_t flags_by_chunk; // flag layout: 1 = colour-major within each 64-vertex chunk (only
+                          // when there are no medium or heavy vertices), 0 = 32 bytes per vertex
   int32_t epoch;          // epoch of this call (written to ctrl by the init kernel)
   int32_t clear_seen;     // the init kernel zeroes `seen` and `wide` (first call, epoch wrap)
   uint8_t* wide;          // (mcount + hcount) * kWideColors flags for colours 32..511

@@ -226,7 +226,7 @@ __device__ void light_phase(const KArgs& a, long wave_gid, long nwaves, Tally& t
     RP b = 0, e = 0;
     if (v < a.n) {
       s = st[v];
-      if (PHASE == kSpec && push && s < 0) {
+      if (PHASE == kSpec && push && s < 0 && !a.flags_by_chunk) {
         // pushed flags: the least colour absent from the final neighbours is
         // the first colour not flagged, unless all of 0..31 are taken; those
         // vertices (light ones here) scan their row from colour 32
@@ -236,6 +236,28 @@ __device__ void light_phase(const KArgs& a, long wave_gid, long nwaves, Tally& t
           s = 0;
         }
       }
+    }
+    if (PHASE == kSpec && push && a.flags_by_chunk) {
+      // the same from the chunk's colour rows, eight rows in flight per
+      // step, until every uncoloured vertex of the chunk has found a colour
+      // not flagged
+      const uint8_t* row = a.seen + (size_t)ch * kPushColors * kWave + lane;
+      int t = -1;
+      const bool need = v < a.n && s < 0;
+      for (int c0 = 0; c0 < kPushColors && __ballot(need && t < 0); c0 += 8) {
+        int f[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) f[j] = row[(size_t)(c0 + j) * kWave];
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          if (t < 0 && f[j] != epoch) t = c0 + j;
+      }
+      if (need && t >= 0) {
+        st[v] = (S)~t;
+        s = 0;
+      }
+    }
+    if (v < a.n) {
       if (s < 0) {
         b = rp[v];
         e = rp[v + 1];
@@ -701,7 +723,8 @@ __global__ void k_init(KArgs a) {
   for (long i = tid; i < kTraceRounds; i += nth) a.ctrl->trace[i] = 0;
   if (a.push && a.clear_seen) {
     uint4* p = (uint4*)a.seen;  // kPushColors bytes per vertex = 2 x 16 bytes
-    for (long i = tid; i < 2l * a.n; i += nth) p[i] = make_uint4(0, 0, 0, 0);
+    const long nv = ((long)a.n + kWave - 1) / kWave * kWave;  // whole chunks
+    for (long i = tid; i < 2l * nv; i += nth) p[i] = make_uint4(0, 0, 0, 0);
     uint4* q = (uint4*)a.wide;  // kWideColors = 30 x 16 bytes per block
     const long nw = (long)(a.mcount + a.hcount) * (kWideColors / 16);
     for (long i = tid; i < nw; i += nth) q[i] = make_uint4(0, 0, 0, 0);
