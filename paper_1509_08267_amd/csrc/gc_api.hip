@@ -671,8 +671,10 @@ extern "C" int gc_color(gc_handle h, int32_t* colors_out, void* stream) {
     LCHECK(h, gc::persistent_max_grid(h->rp64, h->sbytes, L, &maxg));
     // The occupancy query admits more workgroups per CU than are co-resident in
     // practice (a barrier with 7-8 per CU never completes on MI355X), so the
-    // grid is capped at persist_per_cu per CU, which has been verified.
-    int pg = std::min(maxg, h->cus * h->persist_per_cu);
+    // grid is capped at persist_per_cu per CU, which has been verified, and,
+    // like the round kernels', at what the graph can keep busy: a barrier
+    // over fewer workgroups is cheaper.
+    int pg = std::min(std::min(maxg, h->cus * h->persist_per_cu), grid);
     if (pg < 1) return set_err(h, GC_EDEVICE, "persistent kernel cannot be resident");
     LCHECK(h, gc::launch_persistent(a, h->rp64, h->sbytes, L, h->max_rounds, pg, s));
   } else {
