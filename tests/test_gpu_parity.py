@@ -362,6 +362,30 @@ def test_options_changed_between_calls_on_one_handle(gc):
                 assert np.array_equal(out.cpu().numpy(), ref.colors), opts
 
 
+def test_flag_layout_switch_between_calls(gc):
+    # with no medium or heavy vertex the pushed flags are stored colour-major
+    # per 64-vertex chunk, otherwise 32 bytes per vertex; the layout follows
+    # the degree classes from call to call on one handle, and the flags left
+    # by a call in the other layout must never count
+    g = graphgen.er(20000, 200000, 17)
+    ref = oracle.rsc(g.rowptr, g.colidx)
+    rp, ci = _dev(g)
+    steps = [({}, False), ({"medium_degree": 16}, True), ({"medium_degree": 0}, False),
+             ({"medium_degree": 24}, True), ({"lanes": 32}, None)]
+    with gc.Graph(rp, ci, mode="graph") as G:
+        for opts, medium in steps:
+            for k, v in opts.items():
+                G.set(k, v)
+            for _ in range(2):
+                print(f"[case] flag layout, options {opts}", flush=True)
+                out = G.color()
+                r, _ = G.stats()
+                if medium is not None:
+                    assert (G.get(gc.GC_OPT_MEDIUM_COUNT) > 0) == medium, opts
+                assert r == ref.rounds, opts
+                assert np.array_equal(out.cpu().numpy(), ref.colors), opts
+
+
 def test_option_values_are_checked(gc):
     # every option rejects values outside its range with GC_EINVAL and keeps
     # its previous value; the handle still colours correctly afterwards
