@@ -319,7 +319,10 @@ __device__ void light_phase(const KArgs& a, long wave_gid, long nwaves, Tally& t
         tl.lost += lose;
         tl.active += 1;
       }
-      if (push) push_flat<RP, S>(a, st, pb, len, t, epoch);
+      // every entry is pushed, final neighbours included: their flags are
+      // never read again, and a state gather per entry costs more than the
+      // extra stores (measured)
+      if (push) push_flat<RP, S, false>(a, st, pb, len, t, epoch);
       continue;
     }
     const int cnt = __popcll(am);
