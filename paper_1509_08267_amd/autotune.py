@@ -39,7 +39,7 @@ DEFAULT_CANDIDATES = {
     "lanes": [2, 4, 8, 16, 32],
     "medium_degree": [0, 32, 64, 128, 256, 512],   # 0: the library's rule
     "heavy_degree": [1024, 2048, 4096, 8192, 16384],
-    "blocks_per_cu": [2, 4, 8, 16],
+    "blocks_per_cu": [2, 3, 4, 6, 8, 12, 16],
 }
 
 _OPT_IDS = {"lanes": gc.GC_OPT_LANES, "medium_degree": gc.GC_OPT_MEDIUM_DEGREE,
