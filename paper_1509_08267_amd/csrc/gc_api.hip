@@ -554,6 +554,7 @@ static int color_blocks(gc_ctx* h, int32_t* colors_out, int32_t* user_out, hipSt
   h->stats_ready = false;
   KArgs a = make_args(h, colors_out, light_max_of(h, auto_lanes(h)));
   a.st = colors_out;  // the colours are the state (int32)
+  a.clear_trace = 1;  // phase 2 adds each round's size into the trace
   gc::BArgs b{};
   b.rowptr = h->rowptr;
   b.colidx = h->colidx;

@@ -78,6 +78,7 @@ struct KArgs {
                           // when there are no medium or heavy vertices), 0 = 32 bytes per vertex
   int32_t epoch;          // epoch of this call (written to ctrl by the init kernel)
   int32_t clear_seen;     // the init kernel zeroes `seen` and `wide` (first call, epoch wrap)
+  int32_t clear_trace;    // the init kernel zeroes ctrl->trace (p-block passes add into it)
   uint8_t* wide;          // (mcount + hcount) * kWideColors flags for colours 32..511
   const int32_t* widx;    // n: index of v's wide flag block, -1 for light vertices
   int32_t* skip;          // n: lower neighbours before this offset of v's row are final

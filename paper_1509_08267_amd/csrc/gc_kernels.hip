@@ -723,7 +723,10 @@ __global__ void k_fill_tent0(KArgs a) {
 __global__ void k_init(KArgs a) {
   const long tid = blockIdx.x * (long)blockDim.x + threadIdx.x;
   const long nth = (long)gridDim.x * blockDim.x;
-  for (long i = tid; i < kTraceRounds; i += nth) a.ctrl->trace[i] = 0;
+  // round sizes: every round the colouring runs stores its own; only the
+  // p-block passes add into them
+  if (a.clear_trace)
+    for (long i = tid; i < kTraceRounds; i += nth) a.ctrl->trace[i] = 0;
   if (a.push && a.clear_seen) {
     uint4* p = (uint4*)a.seen;  // kPushColors bytes per vertex = 2 x 16 bytes
     const long nv = ((long)a.n + kWave - 1) / kWave * kWave;  // whole chunks
@@ -757,32 +760,44 @@ __device__ __forceinline__ void store_system(int32_t* p, int32_t v) {
 // Widening pass and statistics: the state becomes the caller's int32
 // colours, and each workgroup reports the largest colour and the uncoloured
 // count of its vertices straight into pinned host memory (layout at
-// launch_finish).  A few hundred workgroups, four loads in flight per thread,
-// and no device atomics: the host folds the per-workgroup pairs.
-template <typename S>
+// launch_finish).  Each thread takes 16 bytes of state (16, 8 or 4
+// vertices): one 16-byte load, and 16-byte stores when both arrays are
+// 16-byte aligned (VEC).  No device atomics: the host folds the
+// per-workgroup pairs.
+template <typename S, bool VEC>
 __global__ __launch_bounds__(kBlock) void k_finish(KArgs a, int32_t* out) {
   __shared__ int sh_max[kWavesPerBlock], sh_left[kWavesPerBlock];
   if (blockIdx.x == 0) fold_trace(a);  // the last detect pass's round size
-  constexpr int kU = 4;
+  constexpr int V = 16 / (int)sizeof(S);
   const S* __restrict__ st = (const S*)a.st;
   int mx = -1, left = 0;
   const long nth = (long)gridDim.x * blockDim.x;
-  for (long v0 = blockIdx.x * (long)blockDim.x + threadIdx.x; v0 < a.n; v0 += kU * nth) {
-    int s[kU];
+  const long ngroups = ((long)a.n + V - 1) / V;
+  for (long g = blockIdx.x * (long)blockDim.x + threadIdx.x; g < ngroups; g += nth) {
+    const long v0 = g * V;
+    int s[V];
+    if (VEC && v0 + V <= a.n) {
+      const uint4 w = *(const uint4*)(st + v0);
+      S x[V];
+      __builtin_memcpy(x, &w, sizeof w);
 #pragma unroll
-    for (int q = 0; q < kU; ++q) {
-      const long v = v0 + q * nth;
-      s[q] = v < a.n ? (int)st[v] : 0;
+      for (int q = 0; q < V; ++q) s[q] = x[q];
+#pragma unroll
+      for (int q = 0; q < V; q += 4)
+        *(int4*)(a.colors + v0 + q) = make_int4(s[q], s[q + 1], s[q + 2], s[q + 3]);
+    } else {
+#pragma unroll
+      for (int q = 0; q < V; ++q) s[q] = v0 + q < a.n ? (int)st[v0 + q] : 0;
+#pragma unroll
+      for (int q = 0; q < V; ++q)
+        if (v0 + q < a.n) a.colors[v0 + q] = s[q];
     }
 #pragma unroll
-    for (int q = 0; q < kU; ++q) {
-      const long v = v0 + q * nth;
-      if (v < a.n) {
-        a.colors[v] = s[q];
+    for (int q = 0; q < V; ++q)
+      if (v0 + q < a.n) {
         mx = s[q] > mx ? s[q] : mx;
         left += s[q] < 0;
       }
-    }
   }
 #pragma unroll
   for (int off = kWave / 2; off > 0; off >>= 1) {
@@ -1082,15 +1097,18 @@ int launch_advance_base(const KArgs& a, int by, void* stream) {
 
 int launch_finish(const KArgs& a, int sbytes, int32_t* out, void* stream) {
   hipStream_t s = (hipStream_t)stream;
-  // about 16 vertices per thread, at most kFinishBlocks workgroups
-  const long per = 16l * kBlock;
+  if (sbytes != 1 && sbytes != 2 && sbytes != 4) return (int)hipErrorInvalidValue;
+  // 16 bytes of state per thread, at most kFinishBlocks workgroups
+  const long per = (16l / sbytes) * kBlock;
   const int grid = (int)std::max<long>(1, std::min<long>(kFinishBlocks, ((long)a.n + per - 1) / per));
-  switch (sbytes) {
-    case 1: hipLaunchKernelGGL(k_finish<int8_t>, dim3(grid), dim3(kBlock), 0, s, a, out); break;
-    case 2: hipLaunchKernelGGL(k_finish<int16_t>, dim3(grid), dim3(kBlock), 0, s, a, out); break;
-    case 4: hipLaunchKernelGGL(k_finish<int32_t>, dim3(grid), dim3(kBlock), 0, s, a, out); break;
-    default: return (int)hipErrorInvalidValue;
-  }
+  const bool vec = ((uintptr_t)a.st % 16 == 0) && ((uintptr_t)a.colors % 16 == 0);
+#define GC_FINISH(S_)                                                                     \
+  if (vec) hipLaunchKernelGGL((k_finish<S_, true>), dim3(grid), dim3(kBlock), 0, s, a, out); \
+  else hipLaunchKernelGGL((k_finish<S_, false>), dim3(grid), dim3(kBlock), 0, s, a, out)
+  if (sbytes == 1) GC_FINISH(int8_t);
+  else if (sbytes == 2) GC_FINISH(int16_t);
+  else GC_FINISH(int32_t);
+#undef GC_FINISH
   return (int)hipGetLastError();
 }
 
