@@ -325,6 +325,34 @@ int gc_batch_step(int64_t num_graphs, gc_graph_desc *descs,
                   int32_t *colors_base, int32_t max_rounds, void *workspace,
                   size_t workspace_bytes, void *stream);
 
+/*
+ * gc_copy_segments -- copy many int32 arrays in one launch (staging of many
+ * small requests, e.g. a server admitting graphs whose CSR is already on the
+ * device; not part of the colouring itself).
+ *
+ *   segs     device array of `count` descriptors:
+ *              src          device address of the source words
+ *              dst          device address of the destination words
+ *              words        int32 words to copy (>= 0)
+ *              first_piece  exclusive prefix sum over the descriptors of
+ *                           ceil(words / GC_COPY_PIECE_WORDS)
+ *   pieces   total pieces (the sum of all ceil(words / GC_COPY_PIECE_WORDS))
+ *
+ * Sources and destinations must not overlap.  A workgroup copies one piece
+ * at a time; a piece that lies past its segment's length copies nothing,
+ * so inconsistent prefix sums never write outside [dst, dst + words).
+ * Asynchronous on `stream`; the descriptors must stay valid until it has
+ * run.  Returns GC_OK or GC_EINVAL.
+ */
+#define GC_COPY_PIECE_WORDS 4096
+typedef struct gc_segment {
+  int64_t src;
+  int64_t dst;
+  int64_t words;
+  int64_t first_piece;
+} gc_segment;
+int gc_copy_segments(int64_t count, const gc_segment *segs, int64_t pieces, void *stream);
+
 /* Library version, "major.minor.patch". */
 const char *gc_version(void);
 

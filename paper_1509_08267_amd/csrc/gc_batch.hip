@@ -363,3 +363,47 @@ extern "C" int gc_batch_step(int64_t num_graphs, gc_graph_desc* descs, const int
   if (rc) return fail(GC_EDEVICE, hipGetErrorString((hipError_t)rc));
   return GC_OK;
 }
+
+// ------------------------------------------------- segment copies --
+
+namespace gc {
+
+// Piece p of the concatenated segments: the segment is the last one whose
+// first piece is <= p (binary search, the same in every thread of the
+// workgroup), and the piece covers words [q * P, min((q + 1) * P, words)) of
+// it, q = p - first_piece.
+__global__ __launch_bounds__(kBlock) void k_copy_segments(const gc_segment* __restrict__ seg,
+                                                          int64_t count, int64_t pieces) {
+  for (int64_t p = blockIdx.x; p < pieces; p += gridDim.x) {  // workgroup-uniform
+    int64_t lo = 0, hi = count - 1;
+    while (lo < hi) {
+      const int64_t mid = lo + (hi - lo + 1) / 2;
+      if (seg[mid].first_piece <= p) lo = mid;
+      else hi = mid - 1;
+    }
+    const gc_segment x = seg[lo];
+    const int64_t start = (p - x.first_piece) * GC_COPY_PIECE_WORDS;
+    if (start < 0 || start >= x.words) continue;
+    const int64_t end = start + GC_COPY_PIECE_WORDS < x.words ? start + GC_COPY_PIECE_WORDS : x.words;
+    const int32_t* __restrict__ src = (const int32_t*)x.src;
+    int32_t* __restrict__ dst = (int32_t*)x.dst;
+    for (int64_t k = start + threadIdx.x; k < end; k += blockDim.x) dst[k] = src[k];
+  }
+}
+
+}  // namespace gc
+
+extern "C" int gc_copy_segments(int64_t count, const gc_segment* segs, int64_t pieces,
+                                void* stream) {
+  if (count < 0 || pieces < 0) return fail(GC_EINVAL, "gc_copy_segments: negative count or pieces");
+  if (count == 0 || pieces == 0) return GC_OK;
+  if (!segs) return fail(GC_EINVAL, "gc_copy_segments: NULL descriptors");
+  (void)hipGetLastError();
+  const int grid = (int)(pieces < 4096 ? pieces : 4096);
+  hipLaunchKernelGGL(gc::k_copy_segments, dim3(grid), dim3(gc::kBlock), 0, (hipStream_t)stream,
+                     segs, count, pieces);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(GC_EDEVICE, hipGetErrorString(e));
+  return GC_OK;
+}
+

@@ -10,9 +10,11 @@ the HIP runtime torch has already loaded (both carry the same soname).
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
 
+import numpy as np
 import torch  # noqa: F401  (loads the HIP runtime libgc binds to)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -47,7 +49,8 @@ GC_TRACE_ROUNDS = 65536
 EXPORTS = ["gc_create", "gc_color", "gc_get_stats", "gc_get_round_sizes", "gc_set_option",
            "gc_get_option", "gc_get_profile", "gc_destroy", "gc_last_error",
            "gc_batch_workspace_bytes",
-           "gc_color_batch", "gc_batch_step_workspace_bytes", "gc_batch_step", "gc_version"]
+           "gc_color_batch", "gc_batch_step_workspace_bytes", "gc_batch_step", "gc_copy_segments",
+           "gc_version"]
 
 
 class GCError(RuntimeError):
@@ -92,6 +95,7 @@ def load():
     lib.gc_batch_step_workspace_bytes.argtypes = [i64, i64]
     lib.gc_batch_step_workspace_bytes.restype = sz
     lib.gc_batch_step.argtypes = [i64, p, p, p, p, i32, p, sz, p]
+    lib.gc_copy_segments.argtypes = [i64, p, i64, p]
     lib.gc_version.restype = ctypes.c_char_p
     for name in ("gc_create", "gc_color", "gc_get_stats", "gc_get_round_sizes", "gc_set_option",
                  "gc_get_option", "gc_get_profile", "gc_destroy", "gc_color_batch", "gc_batch_step"):
@@ -207,7 +211,41 @@ def gc_batch_step(num_graphs, descs, rowptr_base, colidx_base, colors_base, max_
                                 _stream(stream)))
 
 
+COPY_PIECE_WORDS = 4096  # GC_COPY_PIECE_WORDS
+
+
+def gc_copy_segments(count: int, segs, pieces: int, stream=None) -> None:
+    _check(load().gc_copy_segments(count, _ptr(segs), pieces, _stream(stream)))
+
+
 # ------------------------------------------------------ convenience ------
+
+def copy_segments(pairs, stream=None):
+    """Copy each (src, dst) pair of int32 device tensors (src.numel() words
+    into the start of dst) with one gc_copy_segments launch on `stream`.
+    Returns the descriptor tensors (pinned host copy, device copy), which
+    must stay alive until the stream has run the copy."""
+    pairs = [(s, d) for s, d in pairs if s.numel() > 0]
+    if not pairs:
+        return None
+    for s, d in pairs:
+        if s.dtype != torch.int32 or d.dtype != torch.int32 or not s.is_cuda or not d.is_cuda:
+            raise ValueError("copy_segments takes int32 device tensors")
+        if d.numel() < s.numel() or not s.is_contiguous() or not d.is_contiguous():
+            raise ValueError("copy_segments: destination too small or not contiguous")
+    words = np.array([s.numel() for s, _ in pairs], dtype=np.int64)
+    per = (words + COPY_PIECE_WORDS - 1) // COPY_PIECE_WORDS
+    first = np.concatenate([[0], np.cumsum(per)[:-1]]).astype(np.int64)
+    desc = np.stack([np.array([s.data_ptr() for s, _ in pairs], dtype=np.int64),
+                     np.array([d.data_ptr() for _, d in pairs], dtype=np.int64),
+                     words, first], axis=1)
+    dev = pairs[0][1].device
+    h_desc = torch.from_numpy(np.ascontiguousarray(desc)).pin_memory()
+    with torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext():
+        d_desc = h_desc.to(dev, non_blocking=True)
+        gc_copy_segments(len(pairs), d_desc, int(per.sum()), stream)
+    return h_desc, d_desc
+
 
 class Graph:
     """A graph bound on the GPU (gc_create) that can be coloured repeatedly.

@@ -158,6 +158,7 @@ class Server:
         self._next_id = 0
         self._ws = None
         self._pending_copy = None                       # event of the last admission copy
+        self._pending_desc = None                       # its segment descriptors (device)
         self.clock = time.perf_counter
 
     # -------------------------------------------------------------- API --
@@ -203,12 +204,21 @@ class Server:
         if not new:
             return
         with torch.cuda.stream(self.copy):
+            # CSR already on the device: every array of the admitted jobs in
+            # one gc_copy_segments launch; host arrays: one copy each
+            staged = []
             for job in new:
                 rpw = _round64(job.n + 1)
-                self.arena[job.offset:job.offset + job.n + 1].copy_(job.rowptr, non_blocking=True)
-                if job.nnz:
-                    self.arena[job.offset + rpw:job.offset + rpw + job.nnz].copy_(
-                        job.colidx, non_blocking=True)
+                rp_dst = self.arena[job.offset:job.offset + job.n + 1]
+                ci_dst = self.arena[job.offset + rpw:job.offset + rpw + job.nnz]
+                for src, dst in ((job.rowptr, rp_dst), (job.colidx, ci_dst)):
+                    if src.numel() == 0:
+                        continue
+                    if src.is_cuda and src.device == self.device:
+                        staged.append((src, dst))
+                    else:
+                        dst.copy_(src, non_blocking=True)
+            self._pending_desc = gc.copy_segments(staged, stream=self.copy)
             ev = torch.cuda.Event()
             ev.record(self.copy)
         self._pending_copy = ev
@@ -231,6 +241,7 @@ class Server:
             if self._pending_copy is not None:
                 self.compute.wait_event(self._pending_copy)
                 self._pending_copy = None
+                self._pending_desc = None  # the copy stream has it; the step waits for it
             d_dev = torch.from_numpy(self.table.view(np.uint8)).to(self.device, non_blocking=False)
             self._ws = gc.batch_step(d_dev, self.arena, self.arena, self.arena,
                                      self.rounds_per_step, workspace=self._ws,

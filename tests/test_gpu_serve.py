@@ -73,3 +73,52 @@ def test_oversized_job_is_rejected(serve):
     with pytest.raises(gc.GCError) as ei:
         srv.submit(g.rowptr, g.colidx)
     assert ei.value.code == gc.GC_ETOOBIG
+
+
+def test_copy_segments_exact(serve):
+    # many int32 arrays copied by one gc_copy_segments launch: lengths around
+    # the 4096-word piece, empty and large ones; the words between the
+    # destinations stay untouched
+    from paper_1509_08267_amd import gc
+    rng = np.random.default_rng(5)
+    lens = [0, 1, 63, 4095, 4096, 4097, 8192, 12289, 0, 200_001, 7, 3]
+    dev = torch.device("cuda:0")
+    srcs = [torch.from_numpy(rng.integers(-2**31, 2**31 - 1, size=n, dtype=np.int64)
+                             .astype(np.int32)).to(dev) for n in lens]
+    gap = 17
+    total = sum(lens) + gap * (len(lens) + 1)
+    out = torch.full((total,), -7, dtype=torch.int32, device=dev)
+    pairs, pos, spans = [], gap, []
+    for s in srcs:
+        pairs.append((s, out[pos:pos + s.numel()]))
+        spans.append((pos, s.numel()))
+        pos += s.numel() + gap
+    keep = gc.copy_segments(pairs)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    mask = np.ones(total, bool)
+    for (p, n), s in zip(spans, srcs):
+        assert np.array_equal(got[p:p + n], s.cpu().numpy()), n
+        mask[p:p + n] = False
+    assert (got[mask] == -7).all()
+    del keep
+
+
+def test_copy_segments_inconsistent_pieces_stay_in_bounds(serve):
+    # a descriptor whose first_piece values do not match the lengths copies
+    # less, never more: every write stays inside its destination
+    from paper_1509_08267_amd import gc
+    dev = torch.device("cuda:0")
+    a = torch.arange(10000, dtype=torch.int32, device=dev)
+    out = torch.full((30000,), -1, dtype=torch.int32, device=dev)
+    # segment 0 claims one piece but has three; segment 1 starts at piece 1
+    desc = np.array([[a.data_ptr(), out.data_ptr(), 10000, 0],
+                     [a.data_ptr(), out[20000:].data_ptr(), 5000, 1]], dtype=np.int64)
+    d = torch.from_numpy(desc).to(dev)
+    gc.gc_copy_segments(2, d, 3)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    assert np.array_equal(got[:4096], np.arange(4096))      # piece 0 of segment 0
+    assert (got[4096:20000] == -1).all()                    # its other pieces were not listed
+    assert np.array_equal(got[20000:25000], np.arange(5000))  # segment 1, pieces 1..2
+    assert (got[25000:] == -1).all()
