@@ -106,7 +106,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the colouring of "
-              "one graph is not sharded across GPUs in this build", file=sys.stderr)
+              "one graph is not sharded across GPUs by this library", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
