@@ -158,7 +158,10 @@ enum gc_option {
   GC_OPT_MEDIUM_COUNT = 9,   /* (get only) vertices on the wavefront path           */
   GC_OPT_HEAVY_COUNT = 10,   /* (get only) vertices on the workgroup path           */
   GC_OPT_PERSISTENT_BLOCKS_PER_CU = 11, /* workgroups per CU of the persistent kernel,
-                                1..6 (4); more are not reliably co-resident   */
+                                1..4 (4); the library lowers it further to what
+                                the kernel's register use lets a CU hold at once
+                                (every workgroup of a grid barrier must be
+                                resident): 3 with int64 row pointers          */
   GC_OPT_STATE_BYTES = 12,   /* (get only) bytes per vertex of the working state:
                                 1 if max degree <= 126, 2 if <= 32766, else 4 */
   GC_OPT_PROFILE = 13,       /* 1: time the kernels of each call with HIP events

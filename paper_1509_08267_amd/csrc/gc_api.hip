@@ -221,6 +221,7 @@ static KArgs make_args(const gc_ctx* h, int32_t* colors, int light_max) {
   a.epoch = h->epoch;
   a.clear_seen = h->epoch == 1;
   a.wide = h->wide;
+  a.wide_clear = (int32_t)h->wide_blocks;
   a.widx = h->widx;
   a.skip = h->skip;
   a.part = h->part;
@@ -670,11 +671,11 @@ extern "C" int gc_color(gc_handle h, int32_t* colors_out, void* stream) {
   if (mode == GC_MODE_PERSISTENT) {
     int maxg = 0;
     LCHECK(h, gc::persistent_max_grid(h->rp64, h->sbytes, L, &maxg));
-    // The occupancy query admits more workgroups per CU than are co-resident in
-    // practice (a barrier with 7-8 per CU never completes on MI355X), so the
-    // grid is capped at persist_per_cu per CU, which has been verified, and,
-    // like the round kernels', at what the graph can keep busy: a barrier
-    // over fewer workgroups is cheaper.
+    // persistent_max_grid bounds the grid by what the kernel's register and
+    // LDS use let every CU hold at once (3 or 4 workgroups per CU); the
+    // option can only lower that, and, as for the round kernels, the grid
+    // stops at what the graph can keep busy: a barrier over fewer workgroups
+    // is cheaper.
     int pg = std::min(std::min(maxg, h->cus * h->persist_per_cu), grid);
     if (pg < 1) return set_err(h, GC_EDEVICE, "persistent kernel cannot be resident");
     LCHECK(h, gc::launch_persistent(a, h->rp64, h->sbytes, L, h->max_rounds, pg, s));
@@ -856,7 +857,7 @@ extern "C" int gc_set_option(gc_handle h, int option, int64_t value) {
       h->chunk_rounds = (int)value;
       return GC_OK;
     case GC_OPT_PERSISTENT_BLOCKS_PER_CU:
-      if (value < 1 || value > 6) break;
+      if (value < 1 || value > 4) break;
       h->persist_per_cu = (int)value;
       return GC_OK;
     case GC_OPT_ALGORITHM:

@@ -80,6 +80,9 @@ struct KArgs {
   int32_t clear_seen;     // the init kernel zeroes `seen` and `wide` (first call, epoch wrap)
   int32_t clear_trace;    // the init kernel zeroes ctrl->trace (p-block passes add into it)
   uint8_t* wide;          // (mcount + hcount) * kWideColors flags for colours 32..511
+  int32_t wide_clear;     // wide blocks allocated: the init kernel's clear covers all of them,
+                          // so a block left over from a larger degree-class split of an
+                          // earlier call cannot keep a byte equal to a later epoch
   const int32_t* widx;    // n: index of v's wide flag block, -1 for light vertices
   int32_t* skip;          // n: lower neighbours before this offset of v's row are final
                           // (sorted rows); zeroed by round 1

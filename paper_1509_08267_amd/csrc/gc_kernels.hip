@@ -732,7 +732,7 @@ __global__ void k_init(KArgs a) {
     const long nv = ((long)a.n + kWave - 1) / kWave * kWave;  // whole chunks
     for (long i = tid; i < 2l * nv; i += nth) p[i] = make_uint4(0, 0, 0, 0);
     uint4* q = (uint4*)a.wide;  // kWideColors = 30 x 16 bytes per block
-    const long nw = (long)(a.mcount + a.hcount) * (kWideColors / 16);
+    const long nw = (long)a.wide_clear * (kWideColors / 16);
     for (long i = tid; i < nw; i += nth) q[i] = make_uint4(0, 0, 0, 0);
   }
   if (tid == 0) {
@@ -1026,6 +1026,30 @@ static int launch_persistent_t(const KArgs& a, int max_rounds, int grid, hipStre
                                          dim3(kBlock), args, 0, s);
 }
 
+// Workgroups of `kernel` (kBlock threads, no dynamic LDS) that one compute
+// unit of a gfx950 can hold at once, from the kernel's own register and LDS
+// use: a SIMD's register file holds 512 registers per lane, allocated to a
+// wave in granules of 8 (architectural and accumulation registers together),
+// and runs at most 8 waves; a CU has 4 SIMDs and 160 KB of LDS.  Returns 0
+// when the attributes cannot be read.
+static int resident_blocks_per_cu(const void* kernel) {
+  hipFuncAttributes fa;
+  if (hipFuncGetAttributes(&fa, kernel) != hipSuccess || fa.numRegs <= 0) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  const int regs = (fa.numRegs + 7) / 8 * 8;
+  const int waves_per_simd = std::min(8, 512 / regs);
+  int blocks = waves_per_simd * 4 / kWavesPerBlock;
+  if (fa.sharedSizeBytes > 0) blocks = std::min<int>(blocks, (int)((160u << 10) / fa.sharedSizeBytes));
+  return blocks;
+}
+
+// Grid of the cooperative kernel: every workgroup must be resident at once,
+// or a grid barrier waits for one that never starts.  The occupancy query
+// alone is not trusted for that: on gfx950 it admitted 8 workgroups per CU of
+// a kernel whose 120-152 registers per lane allow only 3-4 waves per SIMD
+// (the barrier then timed out).  The grid is the smaller of the two bounds.
 template <typename RP, typename S, int L>
 static int persistent_grid_t(int* grid_out) {
   int dev = 0, per_cu = 0, cus = 0;
@@ -1033,9 +1057,11 @@ static int persistent_grid_t(int* grid_out) {
   if (e != hipSuccess) return (int)e;
   e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return (int)e;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)&k_persistent<RP, S, L>,
-                                                   kBlock, 0);
+  const void* kernel = (const void*)&k_persistent<RP, S, L>;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0);
   if (e != hipSuccess) return (int)e;
+  const int derived = resident_blocks_per_cu(kernel);
+  per_cu = derived > 0 ? std::min(per_cu, derived) : std::min(per_cu, 1);
   *grid_out = per_cu * cus;
   return 0;
 }

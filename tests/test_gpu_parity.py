@@ -395,7 +395,7 @@ def test_option_values_are_checked(gc):
     bad = [(gc.GC_OPT_MODE, 9), (gc.GC_OPT_LANES, 3), (gc.GC_OPT_LANES, 128),
            (gc.GC_OPT_HEAVY_DEGREE, 0), (gc.GC_OPT_BLOCKS_PER_CU, 0),
            (gc.GC_OPT_BLOCKS_PER_CU, 65), (gc.GC_OPT_MAX_ROUNDS, -1),
-           (gc.GC_OPT_CHUNK_ROUNDS, 0), (gc.GC_OPT_PERSISTENT_BLOCKS_PER_CU, 7),
+           (gc.GC_OPT_CHUNK_ROUNDS, 0), (gc.GC_OPT_PERSISTENT_BLOCKS_PER_CU, 5),
            (gc.GC_OPT_PROFILE, 2), (gc.GC_OPT_ALGORITHM, 5), (gc.GC_OPT_ALGORITHM, -1),
            (gc.GC_OPT_PARTITIONS, -1), (gc.GC_OPT_ORDER, 3), (99, 0)]
     with gc.Graph(rp, ci) as G:
@@ -411,3 +411,16 @@ def test_option_values_are_checked(gc):
         out = G.color()
         assert G.stats()[0] == ref.rounds
         assert np.array_equal(out.cpu().numpy(), ref.colors)
+
+
+@pytest.mark.parametrize("rp64", [False, True])
+def test_persistent_kernel_on_a_full_grid(gc, rp64):
+    # 400,000 vertices give 6,250 chunks of 64: more workgroups than every
+    # CU can hold, so the cooperative grid is at its co-residency bound
+    # (4 workgroups per CU with int32 row pointers, 3 with int64 ones, from
+    # the kernel's register use), and every per-CU setting below it
+    g = graphgen.er(400_000, 4_000_000, 21)
+    ref = oracle.rsc(g.rowptr, g.colidx)
+    for per_cu in (4, 3, 1):
+        print(f"[case] persistent full grid rp64={rp64} per_cu={per_cu}", flush=True)
+        assert_parity(gc, g, ref, mode="persistent", rp64=rp64, persistent_blocks_per_cu=per_cu)
