@@ -106,15 +106,138 @@ struct GraphRun {
   int max_rounds;
 };
 
+// The row [b, e) read as aligned 16-byte quads: the quad holding entry b
+// starts `lead` entries before it.  Every quad that holds at least one entry
+// of the row lies inside the 16-byte block of an in-bounds entry, so it never
+// leaves the array's last page; entries outside the row are masked.
+struct Quads {
+  const int4* q;
+  int lead;  // entries of the first quad before b
+  int len;   // lead + (e - b): entries from q[0] up to the row's end
+};
+
+__device__ __forceinline__ Quads quads_of(const int32_t* ci, int b, int e) {
+  Quads r;
+  r.lead = (int)(((uintptr_t)(ci + b) >> 2) & 3);
+  r.q = (const int4*)(ci + b - r.lead);
+  r.len = e - b + r.lead;
+  return r;
+}
+
+__device__ __forceinline__ void unpack(const int4 w, int* u) {
+  u[0] = w.x;
+  u[1] = w.y;
+  u[2] = w.z;
+  u[3] = w.w;
+}
+
+// Least colour not final on any neighbour of the row [b, e), by a group of L
+// lanes (gl = lane in group) with 16-byte loads, two quads per lane in
+// flight.  Every lane returns the result.
+template <typename S>
+__device__ __forceinline__ int spec_quads(const int32_t* __restrict__ ci, const S* __restrict__ st,
+                                          int b, int e, int L, int gl) {
+  const Quads r = quads_of(ci, b, e);
+  const int nq = (r.len + 3) >> 2;
+  int base = 0;
+  for (;;) {
+    uint64_t m = 0;
+    auto mark = [&](const int4 w, int idx0) {
+      int u[4];
+      unpack(w, u);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int idx = idx0 + j;
+        if (idx >= r.lead && idx < r.len) {
+          const int c = st[u[j]];
+          const unsigned rel = (unsigned)c - (unsigned)base;
+          if (c >= 0 && rel < 64u) m |= 1ull << rel;
+        }
+      }
+    };
+    for (int i = gl; i < nq; i += 2 * L) {
+      const int4 w0 = r.q[i];
+      if (i + L < nq) {
+        const int4 w1 = r.q[i + L];
+        mark(w0, 4 * i);
+        mark(w1, 4 * (i + L));
+      } else {
+        mark(w0, 4 * i);
+      }
+    }
+    for (int off = L / 2; off > 0; off >>= 1) m |= shfl_xor64(m, off);
+    if (m != ~0ull) return base + __builtin_ctzll(~m);
+    base += 64;  // all of base..base+63 are taken: slide the window
+  }
+}
+
+// Conflict scan of v (tentative colour t) over its lower neighbours, rows
+// ascending, by a group of L lanes (lanes gbase .. gbase + L - 1, mask
+// gmask) with 16-byte loads: each step covers L consecutive quads.  With
+// `skip` (not null) the scan starts at offset *skip of the row, every lower
+// neighbour before it being final, and leaves there the offset of the first
+// lower neighbour seen still uncoloured, or of the point where the scan
+// stopped when it saw none (the per-graph path's resume rule: final colours
+// never change).  Stops at the first conflict or the first id >= v.
+template <typename S>
+__device__ __forceinline__ bool detect_quads(const int32_t* __restrict__ ci,
+                                             const S* __restrict__ st, int b, int e, int v, int t,
+                                             int L, int gl, uint64_t gmask, int gbase, int* skip) {
+  const int from = skip ? *skip : 0;
+  const Quads r = quads_of(ci, b + from, e);
+  int first = -1;  // row offset of the first uncoloured lower neighbour seen
+  for (int k0 = 0; k0 < r.len; k0 += 4 * L) {  // group-uniform
+    const int k = k0 + 4 * gl;
+    int u[4] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MAX};
+    if (k < r.len) unpack(r.q[k >> 2], u);
+    int ja = 4, jc = 4, jp = 4;  // this lane's first uncoloured / conflict / past entry
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int idx = k + j;
+      if (idx < r.lead) continue;  // before the scan's start
+      const bool in = idx < r.len;
+      const bool low = in && u[j] < v;
+      const int s = low ? (int)st[u[j]] : 0;
+      if (low && s < 0 && ja == 4) ja = j;
+      // decode, do not test the sign: a neighbour that wins in this same
+      // pass flips ~t to t concurrently and must still count
+      if (low && tent_of(s) == t && jc == 4) jc = j;
+      if (!low && jp == 4) jp = j;
+    }
+    const uint64_t am = (__ballot(ja < 4) & gmask) >> gbase;
+    const uint64_t cm = (__ballot(jc < 4) & gmask) >> gbase;
+    const uint64_t pm = (__ballot(jp < 4) & gmask) >> gbase;
+    // offsets in the row of the first such entries (rows ascend, so every
+    // lower entry precedes the first past one)
+    auto pos = [&](uint64_t mask, int jl) {
+      const int lane = __builtin_ctzll(mask);
+      const int j = __shfl(jl, gbase + lane);
+      return from + k0 + 4 * lane + j - r.lead;
+    };
+    if (first < 0 && am) first = pos(am, ja);
+    if (cm) {
+      if (skip) *skip = first >= 0 ? first : pos(cm, jc);
+      return true;
+    }
+    if (pm) {
+      if (skip) *skip = first >= 0 ? first : pos(pm, jp);
+      return false;
+    }
+  }
+  if (skip) *skip = first >= 0 ? first : e - b;
+  return false;
+}
+
 // One pass (speculate or detect) of one round over the graph's uncoloured
 // vertices by the whole workgroup: each wavefront walks 64-vertex chunks,
 // ballots the uncoloured ones and hands them to its groups of L lanes.
-template <typename S, int L, bool SPEC>
-__device__ __forceinline__ bool graph_pass(const GraphRun& g, S* st) {
+// `skipv` (or null) holds each vertex's resume offset for the detect scans.
+template <typename S, bool SPEC>
+__device__ __forceinline__ bool graph_pass(const GraphRun& g, S* st, int32_t* skipv, int L) {
   const int lane = lane_id();
   const int gl = lane & (L - 1);
   const int grp = lane / L;
-  constexpr int Gw = kWave / L;
+  const int Gw = kWave / L;
   const uint64_t gmask = (L == kWave) ? ~0ull : (((1ull << L) - 1) << (grp * L));
   const int wave = threadIdx.x / kWave;
   bool lost = false;
@@ -141,15 +264,19 @@ __device__ __forceinline__ bool graph_pass(const GraphRun& g, S* st) {
       const int ve = __shfl(e, pos);
       const int vs = __shfl(s, pos);
       const int vv = ch * kWave + pos;
-      if (valid) {
+      if (valid) {  // group-uniform
         if (SPEC) {
-          const int t = spec_group<int32_t, S, L>(g.ci, st, vb, ve, gl);
+          const int t = spec_quads<S>(g.ci, st, vb, ve, L, gl);
           if (gl == 0) st[vv] = (S)~t;
         } else {
           const int t = ~vs;
-          const bool lose = detect_group<int32_t, S, L>(g.ci, st, vb, ve, vv, t, gl, gmask, true);
+          int sk = skipv ? skipv[vv] : 0;
+          const int sk0 = sk;
+          const bool lose = detect_quads<S>(g.ci, st, vb, ve, vv, t, L, gl, gmask, grp * L,
+                                            skipv ? &sk : nullptr);
           if (gl == 0) {
             if (!lose) st[vv] = (S)t;
+            if (skipv && sk != sk0) skipv[vv] = sk;
             lost |= lose;
           }
         }
@@ -161,9 +288,12 @@ __device__ __forceinline__ bool graph_pass(const GraphRun& g, S* st) {
 
 // Rounds of one graph until done or max_rounds more rounds have run.
 // Returns the rounds completed; *left receives the vertices still uncoloured.
-template <typename S, int L, bool IN_LDS>
-__device__ __forceinline__ int run_graph(const GraphRun& g, S* st, int* left) {
+// A graph whose state is in LDS keeps each vertex's resume offset in its
+// colour array during the rounds (the array receives the state at the end).
+template <typename S, bool IN_LDS>
+__device__ __forceinline__ int run_graph(const GraphRun& g, S* st, int L, int* left) {
   __shared__ int sh_cnt;
+  int32_t* const skipv = IN_LDS ? g.out : nullptr;
   bool any = false;
   int r = g.rounds_in;
   if (r == 0) {
@@ -173,22 +303,26 @@ __device__ __forceinline__ int run_graph(const GraphRun& g, S* st, int* left) {
       const int b = g.rp[v], e = g.rp[v + 1];
       const bool lose = e > b && g.ci[b] < v;
       st[v] = lose ? (S)-1 : (S)0;
+      if (IN_LDS) skipv[v] = 0;
       any |= lose;
     }
     r = g.n > 0 ? 1 : 0;
   } else {
     for (int v = threadIdx.x; v < g.n; v += blockDim.x) {
       const int s = g.out[v];
-      if (IN_LDS) st[v] = (S)s;
+      if (IN_LDS) {
+        st[v] = (S)s;
+        skipv[v] = 0;
+      }
       any |= s < 0;
     }
   }
   bool more = __syncthreads_or(any);
   while (more && (g.max_rounds <= 0 || r - g.rounds_in < g.max_rounds)) {
     ++r;
-    graph_pass<S, L, true>(g, st);
+    graph_pass<S, true>(g, st, skipv, L);
     __syncthreads();
-    const bool lost = graph_pass<S, L, false>(g, st);
+    const bool lost = graph_pass<S, false>(g, st, skipv, L > 4 ? L / 2 : L);
     more = __syncthreads_or(lost);
   }
   if (threadIdx.x == 0) sh_cnt = 0;
@@ -206,13 +340,13 @@ __device__ __forceinline__ int run_graph(const GraphRun& g, S* st, int* left) {
   return r;
 }
 
-template <int L>
-__device__ __forceinline__ int dispatch_state(const GraphRun& g, int maxdeg, char* smem, int* left) {
-  if (maxdeg <= 127 && g.n <= kBatchLds) return run_graph<int8_t, L, true>(g, (int8_t*)smem, left);
+__device__ __forceinline__ int dispatch_state(const GraphRun& g, int maxdeg, char* smem, int L,
+                                              int* left) {
+  if (maxdeg <= 127 && g.n <= kBatchLds) return run_graph<int8_t, true>(g, (int8_t*)smem, L, left);
   if (maxdeg <= 32767 && 2 * g.n <= kBatchLds)
-    return run_graph<int16_t, L, true>(g, (int16_t*)smem, left);
-  if (4 * g.n <= kBatchLds) return run_graph<int32_t, L, true>(g, (int32_t*)smem, left);
-  return run_graph<int32_t, L, false>(g, g.out, left);
+    return run_graph<int16_t, true>(g, (int16_t*)smem, L, left);
+  if (4 * g.n <= kBatchLds) return run_graph<int32_t, true>(g, (int32_t*)smem, L, left);
+  return run_graph<int32_t, false>(g, g.out, L, left);
 }
 
 __global__ __launch_bounds__(kBatchBlock, 8) void k_batch_color(int64_t G, gc_graph_desc* d,
@@ -248,10 +382,10 @@ __global__ __launch_bounds__(kBatchBlock, 8) void k_batch_color(int64_t G, gc_gr
     const int64_t nnz = g.n > 0 ? (int64_t)g.rp[g.n] : 0;
     const double avg = g.n > 0 ? (double)nnz / g.n : 0.0;
     int left = 0, rounds;
-    if (avg >= 32.0) rounds = dispatch_state<16>(g, maxdeg, smem, &left);
-    else if (avg >= 16.0) rounds = dispatch_state<8>(g, maxdeg, smem, &left);
-    else if (avg >= 8.0) rounds = dispatch_state<4>(g, maxdeg, smem, &left);
-    else rounds = dispatch_state<2>(g, maxdeg, smem, &left);
+    // lanes per vertex: about two quads (eight entries) of an average row
+    // per lane
+    const int L = avg >= 64.0 ? 16 : avg >= 32.0 ? 8 : avg >= 16.0 ? 4 : 2;
+    rounds = dispatch_state(g, maxdeg, smem, L, &left);
     if (threadIdx.x == 0) {
       d[gi].rounds = rounds;
       d[gi].active = left;
