@@ -203,6 +203,9 @@ class Server:
             new.append(job)
         if not new:
             return
+        # the request tensors may still be being written by work queued on the
+        # caller's stream: the copies start after it
+        self.copy.wait_stream(torch.cuda.current_stream(self.device))
         with torch.cuda.stream(self.copy):
             # CSR already on the device: every array of the admitted jobs in
             # one gc_copy_segments launch; host arrays: one copy each

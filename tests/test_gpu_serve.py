@@ -122,3 +122,40 @@ def test_copy_segments_inconsistent_pieces_stay_in_bounds(serve):
     assert (got[4096:20000] == -1).all()                    # its other pieces were not listed
     assert np.array_equal(got[20000:25000], np.arange(5000))  # segment 1, pieces 1..2
     assert (got[25000:] == -1).all()
+
+
+class _DevReq:
+    def __init__(self, rowptr, colidx):
+        self.rowptr, self.colidx = rowptr, colidx
+
+
+def _device_requests(gs, stream):
+    # the request tensors are written by work queued on `stream` (a copy
+    # from pageable memory and an in-place add), as a producer would
+    reqs = []
+    with torch.cuda.stream(stream):
+        for g in gs:
+            rp = torch.from_numpy(g.rowptr.astype(np.int32)).cuda(non_blocking=False)
+            ci = torch.from_numpy(g.colidx.astype(np.int32) - 1).cuda()
+            ci.add_(1)
+            reqs.append(_DevReq(rp, ci))
+    return reqs
+
+
+@pytest.mark.parametrize("midflight", [False, True])
+def test_device_staged_requests(serve, midflight):
+    # requests whose CSR already lives on the GPU are admitted by one copy
+    # launch per admission; the copy waits for the producer's stream
+    gs = graphs(40, 7)
+    producer = torch.cuda.current_stream()
+    reqs = _device_requests(gs, producer)
+    biggest = max(serve.job_words(g.n, g.nnz) for g in gs)
+    srv = serve.Server(budget_bytes=4 * 4 * biggest, max_slots=12, rounds_per_step=2)
+    arrivals = (np.sort(np.random.default_rng(8).uniform(0, 0.03, len(gs))) if midflight
+                else np.zeros(len(gs)))
+    jobs = srv.serve(reqs, arrivals)
+    for g, j in zip(gs, jobs):
+        ref = oracle.rsc(g.rowptr, g.colidx)
+        assert j.rounds == ref.rounds
+        assert np.array_equal(j.colors, ref.colors)
+    assert srv.alloc.used == 0 and srv.idle()
