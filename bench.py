@@ -11,13 +11,22 @@ roofline     the dominant round kernel (speculate or detect, by measured
              time): algorithmic bytes of its launches / their total time
              measured with HIP events around each launch in a second timed
              region, against 8 TB/s HBM
-cpu_baseline the oracle (plain single-thread C) on the same graph
+step_counters  the whole colouring's HBM bytes from the committed rocprofv3
+             FETCH_SIZE / WRITE_SIZE summary (when it was taken on the same
+             kernel source and launch setting) over the measured step time
+batched      (default workload) the 4,096-graph batch: one gc_color_batch
+             launch, the same graphs through the per-graph path, and the
+             continuous-batching server (burst and Poisson arrivals, requests
+             staged on the device or in pinned host memory) with p50/p99
+cpu_baseline the oracle (plain single-thread C) on the same graph, in a child
+             process pinned to one host core
 """
 import argparse
 import hashlib
 import json
 import os
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -25,6 +34,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "GTEPS + vertices colored/s vs HBM roofline; colors used; batched p99 latency"
+DEFAULT_WORKLOAD = "er_1m_16m"
+BATCH_WORKLOAD = "er_batch_4096"
 
 
 def parse():
@@ -32,7 +43,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=50)
     p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--workload", default="er_1m_16m")
+    p.add_argument("--workload", default=DEFAULT_WORKLOAD)
     p.add_argument("--mode", default="graph")
     p.add_argument("--algorithm", default="auto",
                    choices=["auto", "pull", "push", "seq", "blocks"],
@@ -41,6 +52,8 @@ def parse():
                         "blocks (p = 16384)")
     p.add_argument("--lanes", type=int, default=0,
                    help="fixed lanes per light vertex (turns the autotuner off)")
+    p.add_argument("--blocks-per-cu", type=int, default=0,
+                   help="fixed workgroups per CU of the round kernels (with --lanes)")
     p.add_argument("--no-autotune", action="store_true",
                    help="keep the library's automatic settings instead of tuning them "
                         "(untimed) on the workload first")
@@ -53,6 +66,8 @@ def parse():
     p.add_argument("--batch-only", action="store_true",
                    help="batched workload: time the one-launch batch only (no per-graph "
                         "or served comparison); for profiling runs")
+    p.add_argument("--no-batched", action="store_true",
+                   help="default workload: leave out the batched block")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 1 GiB device copy three times (scales the "
@@ -71,6 +86,20 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "copies": 3}))
 
 
+def host_info():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(),
+            "cores_allowed": len(os.sched_getaffinity(0))}
+
+
 def kernel_source_hash():
     """Hash of the kernel sources and of the engine that picks their launch
     shape; a committed counter summary is used only while it matches."""
@@ -81,11 +110,11 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC
-    summary (``key: value`` lines), if it was taken on the current kernel
-    source."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_pmc.txt")
+def read_summary(name, setting=None):
+    """``key: value`` lines of the committed profile summary profiles/<name>,
+    if it was taken on the current kernel source and, when ``setting`` is
+    given, with the same launch setting (each of its keys must match)."""
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     rec = {}
@@ -96,28 +125,93 @@ def measured_traffic(workload, kernel):
                 rec[k.strip()] = v.strip()
     if rec.get("kernel_source_sha") != kernel_source_hash():
         return None
-    return int(rec["bytes_per_launch"]) if "bytes_per_launch" in rec else None
+    for k, v in (setting or {}).items():
+        if rec.get(k) != str(v):
+            return None
+    return rec
 
 
-def main():
-    args = parse()
-    if args.copy_calibration:
-        copy_calibration()
-        return
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the colouring of "
-              "one graph is not sharded across GPUs by this library", file=sys.stderr)
-        sys.exit(2)
+# ---------------------------------------------------------------- CPU leg --
+
+def _cpu_child(kind, arrays_path, args, core, queue):
+    """Child process: pinned to one host core before anything else runs, it
+    times the oracle on the arrays saved at ``arrays_path``."""
+    os.sched_setaffinity(0, {core})
+    import numpy as np
+
+    import oracle
+    z = np.load(arrays_path, mmap_mode="r")
+    res = {"core": core}
+    if kind == "graph":
+        rp, ci = np.asarray(z["rowptr"]), np.asarray(z["colidx"])
+        algo, order, p = args["algo"], args["order"], args.get("p")
+        ts = []
+        t_start = time.perf_counter()
+        while len(ts) < 3 and time.perf_counter() - t_start < args["budget"]:
+            t = time.perf_counter()
+            if algo == "seq":
+                oracle.seq(rp, ci)
+            elif algo == "blocks":
+                oracle.blocks(rp, ci, p)
+            elif order != "natural":
+                from oracle import ordering
+                ordering.colour_in_order(rp, ci, order, 0,
+                                         lambda rp_, ci_: oracle.rsc(rp_, ci_).colors)
+            else:
+                oracle.rsc(rp, ci)
+            ts.append(time.perf_counter() - t)
+        res["seconds"] = min(ts)
+        res["runs"] = len(ts)
+    else:  # batch sample: graphs one after another, in order
+        voff, eoff = np.asarray(z["voff"]), np.asarray(z["eoff"])
+        rpl, cil = z["rowptr_local"], z["colidx_local"]
+        t_total, edges, done = 0.0, 0, 0
+        while done < voff.shape[0] - 1 and t_total < args["budget"]:
+            n = int(voff[done + 1] - voff[done])
+            r0 = int(voff[done]) + done
+            rp = np.asarray(rpl[r0:r0 + n + 1], dtype=np.int64)
+            ci = np.asarray(cil[int(eoff[done]):int(eoff[done + 1])])
+            t = time.perf_counter()
+            oracle.rsc(rp, ci)
+            t_total += time.perf_counter() - t
+            edges += ci.shape[0] // 2
+            done += 1
+        res.update({"seconds": t_total, "edges": edges, "graphs": done})
+    queue.put(res)
+
+
+def run_cpu_child(kind, arrays, args):
+    """Save ``arrays`` to a temporary .npz, run _cpu_child in a spawned
+    process pinned to the last core this process may use, return its
+    result (or None if it failed)."""
+    import multiprocessing as mp
+
+    import numpy as np
+    core = max(os.sched_getaffinity(0))
+    with tempfile.TemporaryDirectory(prefix="gc_bench_cpu_") as tmp:
+        path = os.path.join(tmp, "arrays.npz")
+        np.savez(path, **arrays)
+        ctx = mp.get_context("spawn")
+        q = ctx.Queue()
+        proc = ctx.Process(target=_cpu_child, args=(kind, path, args, core, q))
+        proc.start()
+        try:
+            res = q.get(timeout=600)
+        except Exception:
+            res = None
+        proc.join(timeout=60)
+    return res
+
+
+# ------------------------------------------------------- one-graph path --
+
+def graph_record(args, golden, host):
     import numpy as np
     import torch
 
     import graphgen
     from paper_1509_08267_amd import gc
 
-    with open(os.path.join(ROOT, "tests", "golden", "workloads.json")) as f:
-        golden = json.load(f)[args.workload]
-    if args.workload == "er_batch_4096":
-        return run_batch(args, golden)
     g = graphgen.workload(args.workload)
     if g.sha256() != golden["input_sha256"]:
         raise SystemExit("generated input does not match the recorded workload")
@@ -128,7 +222,10 @@ def main():
     out = torch.empty(g.n, dtype=torch.int32, device=dev)
 
     extra = {"partitions": golden["blocks_p"]} if args.algorithm == "blocks" else {}
-    G = gc.Graph(rp, ci, mode=args.mode, algorithm=args.algorithm, lanes=args.lanes, **extra)
+    if args.blocks_per_cu:
+        extra["blocks_per_cu"] = args.blocks_per_cu
+    opts = dict(mode=args.mode, algorithm=args.algorithm, lanes=args.lanes, **extra)
+    G = gc.Graph(rp, ci, **opts)
     if args.order != "natural":
         if args.algorithm not in ("auto", "push", "pull"):
             raise SystemExit("--order is recorded for the speculative colouring only")
@@ -141,32 +238,63 @@ def main():
         tuned = dict(res.setting, cached=res.cached, measurements=len(res.table),
                      ms_start=None if res.cached else round(res.baseline_seconds * 1e3, 4),
                      ms_best=round(res.seconds * 1e3, 4))
-    t0 = time.perf_counter()
+    lanes = G.get(gc.GC_OPT_LANES)
+    G_medium = G.get(gc.GC_OPT_MEDIUM_DEGREE)
+    G_heavy = G.get(gc.GC_OPT_HEAVY_DEGREE)
+    G_bpc = G.get(gc.GC_OPT_BLOCKS_PER_CU)
+
+    # a cold call: the first colouring on a fresh handle with the same
+    # setting, which still has to discover the round count R
+    with gc.Graph(rp, ci, **opts) as G0:
+        if args.order != "natural":
+            G0.set("order", args.order)
+        for k, v in (("lanes", lanes), ("medium_degree", G_medium), ("heavy_degree", G_heavy),
+                     ("blocks_per_cu", G_bpc)):
+            if args.algorithm != "blocks" or k == "blocks_per_cu":
+                G0.set(k, v)
+        if args.order != "natural":  # the relabelling is set-up, not the cold colouring
+            G0.set("max_rounds", 1)
+            G0.color(out)
+            try:
+                G0.stats()
+            except gc.GCError:
+                pass
+            G0.set("max_rounds", 0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        G0.color(out)
+        G0.stats()
+        t_cold = time.perf_counter() - t0
+
     G.color(out)
     rounds, ncolors = G.stats()
-    t_first = time.perf_counter() - t0
     for _ in range(args.warmup):
         G.color(out)
     G.stats()
-    got = hashlib.sha256(out.cpu().numpy().astype(np.int32).tobytes()).hexdigest()
-    if args.algorithm == "seq":
-        parity = got == golden["seq_colors_sha256"] and rounds == golden["seq_rounds"]
-    elif args.algorithm == "blocks":
-        parity = got == golden["blocks_colors_sha256"] and rounds == golden["blocks_rounds"]
-    elif args.order != "natural":
-        parity = (got == golden[f"order_{args.order}_colors_sha256"]
-                  and rounds == golden[f"order_{args.order}_rounds"])
-    else:
-        parity = got == golden["colors_sha256"] and rounds == golden["rounds"]
+
+    def parity_of(colours):
+        got = hashlib.sha256(colours.cpu().numpy().astype(np.int32).tobytes()).hexdigest()
+        if args.algorithm == "seq":
+            return got == golden["seq_colors_sha256"] and rounds == golden["seq_rounds"]
+        if args.algorithm == "blocks":
+            return got == golden["blocks_colors_sha256"] and rounds == golden["blocks_rounds"]
+        if args.order != "natural":
+            return (got == golden[f"order_{args.order}_colors_sha256"]
+                    and rounds == golden[f"order_{args.order}_rounds"])
+        return got == golden["colors_sha256"] and rounds == golden["rounds"]
+
+    parity = parity_of(out)
 
     # timed region 1: the library's default path, K back-to-back colourings
+    out.fill_(-7)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         G.color(out)
-    G.stats()
+    r_last, _ = G.stats()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    parity_last = parity_of(out) and r_last == rounds
 
     # timed region 2: the same K colourings with a HIP event around every
     # kernel on the launch stream (rounds launched directly, not as a graph)
@@ -186,10 +314,6 @@ def main():
     sbytes = G.get(gc.GC_OPT_STATE_BYTES)
     algo = {gc.GC_ALGO_PUSH: "push", gc.GC_ALGO_PULL: "pull", gc.GC_ALGO_SEQ: "seq",
             gc.GC_ALGO_BLOCKS: "blocks"}[G.get(gc.GC_OPT_ALGORITHM)]
-    lanes = G.get(gc.GC_OPT_LANES)
-    G_medium = G.get(gc.GC_OPT_MEDIUM_DEGREE)
-    G_heavy = G.get(gc.GC_OPT_HEAVY_DEGREE)
-    G_bpc = G.get(gc.GC_OPT_BLOCKS_PER_CU)
     G.close()
 
     t_step = elapsed / args.steps
@@ -265,7 +389,10 @@ def main():
                                  else (spec_ms, spec_launches, spec_bytes))
     calls = max(1, k_launches // max(1, timed_rounds))
     achieved = k_bytes * calls / (k_ms / 1e3) / 1e9 if k_ms > 0 else None
-    traffic = measured_traffic(args.workload, kernel)
+    setting = {"workload": args.workload, "algorithm": algo, "lanes": lanes,
+               "blocks_per_cu": G_bpc}
+    pmc = read_summary(f"{kernel}_{args.workload}_pmc.txt", setting)
+    traffic = int(pmc["bytes_per_launch"]) if pmc and "bytes_per_launch" in pmc else None
     roofline = {
         "kernel": ({"speculate": "k_blk_phase1", "detect": "k_blk_phase2"}[kernel]
                    if algo == "blocks" else kernel),
@@ -287,49 +414,49 @@ def main():
         # bytes the counters saw per launch over the measured launch time
         roofline["traffic_gbs"] = round(traffic / (k_ms / 1e3 / max(1, k_launches)) / 1e9, 1)
         roofline["traffic_frac"] = round(roofline["traffic_gbs"] / HBM_PEAK_GBS, 4)
+        roofline["traffic_over_algorithmic"] = round(traffic / max(1, roofline["alg_bytes_per_launch"]), 2)
     kernels_ms_per_step = {k: round(v[0] / max(1, calls), 4) for k, v in prof.items()}
+    # The whole colouring's counter bytes (every kernel of one colouring,
+    # from the committed FETCH_SIZE / WRITE_SIZE summary of this setting)
+    # over the measured step time: the rocprof-achieved HBM rate.
+    step_pmc = read_summary(f"step_{args.workload}_pmc.txt", setting)
+    step_counters = None
+    if step_pmc and "bytes_per_colouring" in step_pmc:
+        sb = int(step_pmc["bytes_per_colouring"])
+        step_counters = {"bytes_per_colouring": sb, "achieved": round(sb / t_step / 1e9, 1),
+                         "unit": "GB/s", "peak": HBM_PEAK_GBS,
+                         "achieved_frac_counters": round(sb / t_step / 1e9 / HBM_PEAK_GBS, 4)}
     # The whole colouring priced with the pull-based per-unit byte figures
     # (8 B per neighbour visit in speculate and per lower-neighbour visit in
     # detect, plus per uncoloured vertex two rowptr pairs, worklist and state
     # bytes), i.e. what a pull implementation of the same rounds must move,
-    # over the timed step.
+    # over the timed step.  A secondary figure: the push kernels move fewer.
     pull_bytes = (8 * golden["sum_active_deg"] + 8 * golden["sum_active_lower_deg"]
                   + golden["sum_active"] * (2 * (4 + 2 * rp_b + 4) + 4))
-    step_roofline = None if algo in ("seq", "blocks") else {"definition": "pull-equivalent bytes per colouring",
-                     "bytes": pull_bytes,
-                     "achieved": round(pull_bytes / t_step / 1e9, 1), "unit": "GB/s",
-                     "peak": HBM_PEAK_GBS,
-                     "frac": round(pull_bytes / t_step / 1e9 / HBM_PEAK_GBS, 4)}
+    step_roofline = None if algo in ("seq", "blocks") else {
+        "definition": "pull-equivalent bytes per colouring (not the bytes the push kernels move)",
+        "bytes": pull_bytes, "achieved": round(pull_bytes / t_step / 1e9, 1), "unit": "GB/s",
+        "peak": HBM_PEAK_GBS, "frac": round(pull_bytes / t_step / 1e9 / HBM_PEAK_GBS, 4)}
 
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        ts = []
-        budget = 20.0
-        tstart = time.perf_counter()
-        while len(ts) < 3 and (time.perf_counter() - tstart) < budget:
-            t = time.perf_counter()
-            if algo == "seq":
-                oracle.seq(g.rowptr, g.colidx)
-            elif algo == "blocks":
-                oracle.blocks(g.rowptr, g.colidx, golden["blocks_p"])
-            elif args.order != "natural":
-                from oracle import ordering
-                ordering.colour_in_order(g.rowptr, g.colidx, args.order, 0,
-                                         lambda rp_, ci_: oracle.rsc(rp_, ci_).colors)
-            else:
-                oracle.rsc(g.rowptr, g.colidx)
-            ts.append(time.perf_counter() - t)
-        tb = min(ts)
-        cpu = {"value": round(g.m / tb / 1e9, 5), "unit": "GTEPS", "cores": 1, "kind": "oracle",
-               "sample": f"whole {args.workload} graph, oracle "
-                         f"{algo if algo in ('seq', 'blocks') else 'rsc'}"
-                         f"{'' if args.order == 'natural' else ' after relabelling in the ' + args.order + ' order (numpy)'}"
-                         f", best of {len(ts)} single-thread runs "
-                         f"({tb:.2f} s each)",
-               "seconds": round(tb, 3)}
+        res = run_cpu_child("graph", {"rowptr": g.rowptr, "colidx": g.colidx},
+                            {"algo": algo, "order": args.order, "budget": 20.0,
+                             "p": golden.get("blocks_p")})
+        if res:
+            tb = res["seconds"]
+            cpu = {"value": round(g.m / tb / 1e9, 5), "unit": "GTEPS", "cores": 1,
+                   "kind": "oracle",
+                   "sample": f"whole {args.workload} graph, oracle "
+                             f"{algo if algo in ('seq', 'blocks') else 'rsc'}"
+                             f"{'' if args.order == 'natural' else ' after relabelling in the ' + args.order + ' order (numpy)'}"
+                             f", best of {res['runs']} single-thread runs ({tb:.2f} s each)",
+                   "seconds": round(tb, 3), "pinned_core": res["core"], **host,
+                   "paper_context": "the paper reports only CPU speedups of its barrier "
+                                    "algorithm over sequential First Fit (0.56 on LiveJournal, "
+                                    "0.28 on Orkut; Xeon X5675, Section 5.3)"}
 
-    rec = {
+    return {
         "metric": METRIC,
         "value": round(gteps, 3),
         "unit": "GTEPS",
@@ -353,35 +480,33 @@ def main():
         "partitions": golden["blocks_p"] if algo == "blocks" else None,
         "rounds": rounds,
         "parity_vs_oracle": parity,
-        "first_call_ms": round(t_first * 1e3, 3),
+        "parity_last_timed_call": parity_last,
+        "cold_call_ms": round(t_cold * 1e3, 3),
+        "cold_call_gteps": round(g.m / t_cold / 1e9, 3),
         "profiled_ms_per_step": round(elapsed_prof / args.steps * 1e3, 4),
         "kernel_ms_per_step": kernels_ms_per_step,
         # the byte counts are those of the natural order
         "roofline": roofline if args.order == "natural" else None,
+        "step_counters": step_counters if args.order == "natural" else None,
         "step_roofline_pull_equivalent": step_roofline if args.order == "natural" else None,
         "cpu_baseline": cpu,
     }
-    print(json.dumps(rec), flush=True)
 
 
-def run_batch(args, golden):
-    """The batched workload: 4,096 independent ER graphs.
+# ---------------------------------------------------------- batched path --
 
-    value        GTEPS of one gc_color_batch launch over the whole batch
-                 (CSR resident in HBM), summed edges / time
-    per-graph    the same graphs coloured one gc_color call each
-    served       the continuous-batching server fed the graphs as requests
-                 staged on the device, burst and Poisson arrivals
-    """
+def batched_block(args, golden, host, standalone):
+    """The batched workload (4,096 independent ER graphs): one
+    gc_color_batch launch, the per-graph path, and the server."""
     import numpy as np
     import torch
 
     import graphgen
     from paper_1509_08267_amd import gc, serve
 
-    b = graphgen.workload(args.workload)
+    b = graphgen.workload(BATCH_WORKLOAD)
     if b.sha256() != golden["input_sha256"]:
-        raise SystemExit("generated input does not match the recorded workload")
+        raise SystemExit("generated batch does not match the recorded workload")
     G = b.num_graphs
     dev = torch.device("cuda:0")
     d = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(dev)
@@ -397,15 +522,19 @@ def run_batch(args, golden):
     def launch():
         gc.gc_color_batch(G, voff, eoff, rpl, cil, colors, rounds, ws, nbytes)
 
+    def parity_now():
+        return (hashlib.sha256(colors.cpu().numpy().astype(np.int32).tobytes()).hexdigest()
+                == golden["colors_sha256"]
+                and hashlib.sha256(rounds.cpu().numpy().astype(np.int64).tobytes()).hexdigest()
+                == golden["rounds_sha256"])
+
     for _ in range(max(1, args.warmup)):
         launch()
     torch.cuda.synchronize()
-    parity = (hashlib.sha256(colors.cpu().numpy().astype(np.int32).tobytes()).hexdigest()
-              == golden["colors_sha256"]
-              and hashlib.sha256(rounds.cpu().numpy().astype(np.int64).tobytes()).hexdigest()
-              == golden["rounds_sha256"])
+    parity = parity_now()
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     steps = max(1, args.steps // 5)
+    colors.fill_(-7)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     start.record()
@@ -414,14 +543,39 @@ def run_batch(args, golden):
     end.record()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    parity_last = parity_now()
     kernel_ms = start.elapsed_time(end) / steps
     t_step = elapsed / steps
+    ref_colors = colors.clone()
 
-    t_pergraph = None
-    served = None
+    # HBM roofline of the batch kernel: colidx entries the rounds read
+    # (speculate: every neighbour of every uncoloured vertex of rounds >= 2;
+    # detect: the lower-id prefix, an upper bound because the scan stops at
+    # the first conflict) plus each uncoloured vertex's rowptr pair; the
+    # state is in LDS and is not HBM traffic.
+    alg = 4 * (golden["sum_active_deg"] - int(b.eoff[-1]) + golden["sum_active_lower_deg"]) \
+        + 8 * golden["sum_active"]
+    achieved = alg / (kernel_ms / 1e3) / 1e9
+    pmc = read_summary(f"batch_{BATCH_WORKLOAD}_pmc.txt")
+    traffic = int(pmc["bytes_per_launch"]) if pmc and "bytes_per_launch" in pmc else None
+    roofline = {"kernel": "gc_color_batch (k_batch_color)", "bound": "hbm",
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "alg_bytes_per_launch": alg, "avg_launch_us": round(kernel_ms * 1e3, 1),
+                "launches": steps}
+    if traffic:
+        roofline["traffic_gbs"] = round(traffic / (kernel_ms / 1e3) / 1e9, 1)
+        roofline["traffic_frac"] = round(roofline["traffic_gbs"] / HBM_PEAK_GBS, 4)
+    rec = {"workload": BATCH_WORKLOAD, "graphs": G, "n": n, "m": m, "nnz": int(b.eoff[-1]),
+           "ms_per_launch": round(t_step * 1e3, 3),
+           "GTEPS": round(m / t_step / 1e9, 3),
+           "graphs_per_s": round(G / t_step, 1),
+           "vertices_per_s": round(n / t_step, 1),
+           "parity_vs_oracle": parity, "parity_last_timed_launch": parity_last,
+           "colors_max": golden["num_colors_max"], "rounds_max": golden["rounds_max"],
+           "roofline": roofline}
     if args.batch_only:
-        return batch_record(args, golden, b, G, m, n, t_step, kernel_ms, steps, parity,
-                            t_pergraph, served)
+        return rec, t_step, steps
 
     # per-graph path on the same graphs (handles made untimed, rounds known)
     handles = []
@@ -443,105 +597,111 @@ def run_batch(args, golden):
     t_pergraph = time.perf_counter() - t0
     for H, _ in handles:
         H.close()
+    rec["per_graph_path"] = {"ms": round(t_pergraph * 1e3, 2),
+                             "GTEPS": round(m / t_pergraph / 1e9, 3),
+                             "graphs_per_s": round(G / t_pergraph, 1)}
+    rec["batch_gain_over_per_graph"] = round(t_pergraph / t_step, 2)
 
-    # served: requests staged on the device, burst and Poisson arrivals
+    # served: requests staged on the device (or in pinned host memory),
+    # burst and Poisson arrivals at fractions of the one-launch rate
     class Req:
-        def __init__(self, gi):
+        def __init__(self, gi, rp_src, ci_src):
             a0, a1 = int(b.voff[gi]) + gi, int(b.voff[gi + 1]) + gi + 1
-            self.rowptr = rpl[a0:a1]
-            self.colidx = cil[int(b.eoff[gi]):int(b.eoff[gi + 1])]
+            self.rowptr = rp_src[a0:a1]
+            self.colidx = ci_src[int(b.eoff[gi]):int(b.eoff[gi + 1])]
 
-    reqs = [Req(gi) for gi in range(G)]
+    reqs = [Req(gi, rpl, cil) for gi in range(G)]
     K = args.rounds_per_step
-    srv = serve.Server(budget_bytes=12 << 30, max_slots=G, rounds_per_step=K, keep_colors=False)
-    t0 = time.perf_counter()
-    jobs = srv.serve(reqs, np.zeros(G))
-    burst_rate = G / (time.perf_counter() - t0)
-    served = {"requests": "device-staged CSR, copied into the server arena on admission",
-              "rounds_per_step": K, "burst_graphs_per_s": round(burst_rate, 1),
-              "burst": serve.latency_summary(jobs), "poisson": []}
-    for frac in (0.5, 0.8, 0.95):
-        lam = frac * burst_rate
-        arr = graphgen.poisson_arrivals(G, lam, seed=1)
+    batch_rate = G / t_step
+
+    def serve_once(requests, arrivals, keep=False):
         srv = serve.Server(budget_bytes=12 << 30, max_slots=G, rounds_per_step=K,
-                           keep_colors=False)
+                           keep_colors=keep)
         t0 = time.perf_counter()
-        jobs = srv.serve(reqs, arr)
-        dt = time.perf_counter() - t0
-        rec = {"load": frac, "rate_per_s": round(lam, 1), "achieved_per_s": round(G / dt, 1)}
-        rec.update({k: round(v, 3) for k, v in serve.latency_summary(jobs).items()})
-        served["poisson"].append(rec)
-    return batch_record(args, golden, b, G, m, n, t_step, kernel_ms, steps, parity,
-                        t_pergraph, served)
+        jobs = srv.serve(requests, arrivals)
+        return jobs, time.perf_counter() - t0
+
+    jobs, dt = serve_once(reqs, np.zeros(G), keep=True)
+    # every served colouring equals the batch launch's (itself equal to the oracle's)
+    host_ref = ref_colors.cpu().numpy()
+    served_ok = all(np.array_equal(j.colors, host_ref[int(b.voff[i]):int(b.voff[i + 1])])
+                    for i, j in enumerate(jobs))
+    burst_rate = G / dt
+    served = {"requests": "device-staged CSR, copied into the server arena on admission",
+              "rounds_per_step": K, "colours_equal_batch": served_ok,
+              "burst_graphs_per_s": round(burst_rate, 1),
+              "burst": serve.latency_summary(jobs), "poisson": []}
+    served["burst_graphs_per_s"] = round(G / serve_once(reqs, np.zeros(G))[1], 1)
+    for frac in (0.5, 0.8, 0.95):
+        lam = frac * batch_rate
+        arr = graphgen.poisson_arrivals(G, lam, seed=1)
+        jobs, dt = serve_once(reqs, arr)
+        r = {"load": frac, "of": "one-launch batch rate", "rate_per_s": round(lam, 1),
+             "achieved_per_s": round(G / dt, 1)}
+        r.update({k: round(v, 3) for k, v in serve.latency_summary(jobs).items()})
+        served["poisson"].append(r)
+    # host-pinned requests: the host-to-device transfer is inside the latency
+    rpl_h = torch.from_numpy(np.ascontiguousarray(b.rowptr_local, dtype=np.int32)).pin_memory()
+    cil_h = torch.from_numpy(np.ascontiguousarray(b.colidx_local, dtype=np.int32)).pin_memory()
+    hreqs = [Req(gi, rpl_h, cil_h) for gi in range(G)]
+    jobs, dt = serve_once(hreqs, np.zeros(G))
+    served["host_pinned_burst"] = {"graphs_per_s": round(G / dt, 1),
+                                   "GB_per_s_host_to_device": round(
+                                       4 * (rpl_h.numel() + cil_h.numel()) / dt / 1e9, 2),
+                                   **{k: round(v, 3) for k, v in
+                                      serve.latency_summary(jobs).items()}}
+    del rpl_h, cil_h, hreqs
+    rec["served"] = served
+
+    if not args.no_cpu_baseline:
+        # the first graphs of the batch, one after another, about 12 s of
+        # single-thread oracle work (the batch's graph mix in order)
+        k = int(np.searchsorted(np.cumsum(np.diff(b.eoff)), 4.0e8)) + 1
+        k = max(1, min(G, k))
+        arrays = {"voff": b.voff[:k + 1], "eoff": b.eoff[:k + 1],
+                  "rowptr_local": b.rowptr_local[:int(b.voff[k]) + k],
+                  "colidx_local": b.colidx_local[:int(b.eoff[k])]}
+        res = run_cpu_child("batch", arrays, {"budget": 12.0})
+        if res:
+            rec["cpu_baseline"] = {
+                "value": round(res["edges"] / res["seconds"] / 1e9, 5), "unit": "GTEPS",
+                "cores": 1, "kind": "oracle",
+                "sample": f"the first {res['graphs']} of {G} graphs of the batch, each coloured "
+                          f"by the single-thread oracle ({res['seconds']:.1f} s, "
+                          f"{res['edges']} edges)",
+                "seconds": round(res["seconds"], 3), "pinned_core": res["core"], **host}
+    return rec, t_step, steps
 
 
-def batch_record(args, golden, b, G, m, n, t_step, kernel_ms, steps, parity, t_pergraph, served):
-
-    # HBM roofline of the batch kernel: colidx entries the rounds read
-    # (speculate: every neighbour of every uncoloured vertex of rounds >= 2;
-    # detect: the lower-id prefix, an upper bound because the scan stops at
-    # the first conflict) plus each uncoloured vertex's rowptr pair; the
-    # state is in LDS and is not HBM traffic.
-    alg = 4 * (golden["sum_active_deg"] - int(b.eoff[-1]) + golden["sum_active_lower_deg"]) \
-        + 8 * golden["sum_active"]
-    achieved = alg / (kernel_ms / 1e3) / 1e9
-    traffic = measured_traffic(args.workload, "batch")
-    roofline = {"kernel": "gc_color_batch (k_batch_color)", "bound": "hbm",
-                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "alg_bytes_per_launch": alg, "avg_launch_us": round(kernel_ms * 1e3, 1),
-                "launches": steps}
-    if traffic:
-        roofline["traffic_gbs"] = round(traffic / (kernel_ms / 1e3) / 1e9, 1)
-        roofline["traffic_frac"] = round(roofline["traffic_gbs"] / HBM_PEAK_GBS, 4)
-    rec = {
-        "metric": METRIC,
-        "value": round(m / t_step / 1e9, 3),
-        "unit": "GTEPS",
-        "n_gpus": 1,
-        "steps": steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(t_step * 1e3, 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "int32",
-        "data": "synthetic",
-        "config": {"workload": args.workload, "graphs": G, "n": n, "m": m, "nnz": int(b.eoff[-1]),
-                   "seed": 0},
-        "graphs_per_s": round(G / t_step, 1),
-        "vertices_per_s": round(n / t_step, 1),
-        "parity_vs_oracle": parity,
-        "colors_max": golden["num_colors_max"],
-        "rounds_max": golden["rounds_max"],
-        "per_graph_path": None if t_pergraph is None else {
-            "ms": round(t_pergraph * 1e3, 2), "GTEPS": round(m / t_pergraph / 1e9, 3),
-            "graphs_per_s": round(G / t_pergraph, 1)},
-        "batch_gain_over_per_graph": None if t_pergraph is None else round(t_pergraph / t_step, 2),
-        "served": served,
-        "roofline": roofline,
-        "cpu_baseline": None if args.no_cpu_baseline else batch_cpu_baseline(b),
-    }
+def main():
+    args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): this library "
+              "colours each graph on a single GPU, and there is no multi-GPU path to time",
+              file=sys.stderr)
+        sys.exit(2)
+    host = host_info()
+    with open(os.path.join(ROOT, "tests", "golden", "workloads.json")) as f:
+        goldens = json.load(f)
+    if args.workload == BATCH_WORKLOAD:
+        rec, t_step, steps = batched_block(args, goldens[BATCH_WORKLOAD], host, True)
+        out = {"metric": METRIC, "value": rec["GTEPS"], "unit": "GTEPS", "n_gpus": 1,
+               "steps": steps, "warmup": args.warmup, "ms_per_step": rec["ms_per_launch"],
+               "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+               "dtype": "int32", "data": "synthetic",
+               "config": {"workload": BATCH_WORKLOAD, "graphs": rec["graphs"], "n": rec["n"],
+                          "m": rec["m"], "nnz": rec["nnz"], "seed": 0},
+               **{k: v for k, v in rec.items() if k not in ("workload", "graphs", "n", "m", "nnz")}}
+        print(json.dumps(out), flush=True)
+        return
+    rec = graph_record(args, goldens[args.workload], host)
+    if args.workload == DEFAULT_WORKLOAD and not args.no_batched:
+        brec, _, _ = batched_block(args, goldens[BATCH_WORKLOAD], host, False)
+        rec["batched"] = brec
     print(json.dumps(rec), flush=True)
-
-
-def batch_cpu_baseline(b, budget=15.0):
-    """The oracle on the batch's first graphs, one at a time in order, until
-    `budget` seconds of single-thread work; GTEPS over the graphs done."""
-    import oracle
-    t_total, edges, done = 0.0, 0, 0
-    while done < b.num_graphs and t_total < budget:
-        g = b.graph(done)
-        t = time.perf_counter()
-        oracle.rsc(g.rowptr, g.colidx)
-        t_total += time.perf_counter() - t
-        edges += g.nnz // 2
-        done += 1
-    return {"value": round(edges / t_total / 1e9, 5), "unit": "GTEPS", "cores": 1,
-            "kind": "oracle",
-            "sample": f"the first {done} of {b.num_graphs} graphs of the batch, each coloured by "
-                      f"the single-thread oracle ({t_total:.1f} s, {edges} edges)",
-            "seconds": round(t_total, 3)}
 
 
 if __name__ == "__main__":
