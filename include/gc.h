@@ -290,6 +290,28 @@ int gc_color_batch(int64_t num_graphs, const int64_t *voff, const int64_t *eoff,
                    size_t workspace_bytes, void *stream);
 
 /*
+ * gc_color_batch_noalloc -- gc_color_batch without a workspace argument and
+ * without any allocation, for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc).
+ *
+ * The arguments and the result are those of gc_color_batch.  The workspace
+ * is a fixed device array inside the library (about 2.9 MB, one per GPU the
+ * library runs on, held until the process ends), so:
+ *   - num_graphs may not exceed GC_STATIC_BATCH_MAX_GRAPHS (GC_ETOOBIG);
+ *   - calls that overlap in time on one GPU (on different streams, or from
+ *     different threads) share that array and race: order them on one
+ *     stream.  Nothing in it needs to survive between calls; each call
+ *     rewrites what it reads.
+ * No hipMalloc, hipFree or allocating library routine is called.  Returns
+ * GC_OK, GC_EINVAL, GC_ETOOBIG or GC_EDEVICE.  Asynchronous on `stream`.
+ */
+#define GC_STATIC_BATCH_MAX_GRAPHS 65536
+int gc_color_batch_noalloc(int64_t num_graphs, const int64_t *voff, const int64_t *eoff,
+                           const int32_t *rowptr_local, const int32_t *colidx_local,
+                           int32_t *colors_out, int32_t *rounds_out, void *stream);
+
+/*
  * Resumable batch steps for continuous batching.  A graph's whole state
  * between rounds is its colour array (final colours >= 0; a negative entry
  * marks a vertex still to be coloured) plus the count of rounds done, so a

@@ -22,6 +22,7 @@
 
 #include <climits>
 #include <cstdint>
+#include <mutex>
 
 #include "gc.h"
 #include "gc_device.h"
@@ -475,6 +476,59 @@ extern "C" int gc_color_batch(int64_t num_graphs, const int64_t* voff, const int
     if (e != hipSuccess) return fail(GC_EDEVICE, hipGetErrorString(e));
   }
   return GC_OK;
+}
+
+// ------------------------------------------ batch without allocation --
+
+namespace gc {
+
+// Workspace of gc_color_batch_noalloc: a file-scope device array of
+// kStaticBatchBytes, enough for kStaticBatchGraphs graphs.  Each GPU holds
+// its own copy from the first launch of this library's kernels on it until
+// the process ends.
+constexpr int64_t kStaticBatchGraphs = GC_STATIC_BATCH_MAX_GRAPHS;
+constexpr size_t kStaticBatchBytes =
+    ((sizeof(BatchCtrl) + (size_t)kStaticBatchGraphs * sizeof(int32_t) + 255) & ~(size_t)255) +
+    (size_t)kStaticBatchGraphs * sizeof(gc_graph_desc) + 256;
+static __device__ __align__(256) uint8_t scratch[kStaticBatchBytes];
+
+// Device address of `scratch` on each device, looked up once per device with
+// that device current (host code never passes the array's name itself).
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mutex;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+static int static_scratch(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return (int)e;
+  if (dev < 0 || dev >= kMaxDevices) return (int)hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return (int)e;
+    if (!p) return (int)hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return 0;
+}
+
+}  // namespace gc
+
+extern "C" int gc_color_batch_noalloc(int64_t num_graphs, const int64_t* voff, const int64_t* eoff,
+                                      const int32_t* rowptr_local, const int32_t* colidx_local,
+                                      int32_t* colors_out, int32_t* rounds_out, void* stream) {
+  if (num_graphs < 0) return fail(GC_EINVAL, "gc_color_batch_noalloc: bad num_graphs");
+  if (num_graphs > gc::kStaticBatchGraphs)
+    return fail(GC_ETOOBIG, "gc_color_batch_noalloc: more graphs than GC_STATIC_BATCH_MAX_GRAPHS");
+  if (num_graphs == 0) return GC_OK;
+  void* ws = nullptr;
+  const int rc = gc::static_scratch(&ws);
+  if (rc) return fail(GC_EDEVICE, hipGetErrorString((hipError_t)rc));
+  return gc_color_batch(num_graphs, voff, eoff, rowptr_local, colidx_local, colors_out,
+                        rounds_out, ws, gc::kStaticBatchBytes, stream);
 }
 
 extern "C" size_t gc_batch_step_workspace_bytes(int64_t num_graphs, int64_t total_vertices) {

@@ -50,7 +50,7 @@ EXPORTS = ["gc_create", "gc_color", "gc_get_stats", "gc_get_round_sizes", "gc_se
            "gc_get_option", "gc_get_profile", "gc_destroy", "gc_last_error",
            "gc_batch_workspace_bytes",
            "gc_color_batch", "gc_batch_step_workspace_bytes", "gc_batch_step", "gc_copy_segments",
-           "gc_version"]
+           "gc_version", "gc_color_batch_noalloc"]
 
 
 class GCError(RuntimeError):
@@ -92,13 +92,15 @@ def load():
     lib.gc_batch_workspace_bytes.argtypes = [i64, p, p]
     lib.gc_batch_workspace_bytes.restype = sz
     lib.gc_color_batch.argtypes = [i64, p, p, p, p, p, p, p, sz, p]
+    lib.gc_color_batch_noalloc.argtypes = [i64, p, p, p, p, p, p, p]
     lib.gc_batch_step_workspace_bytes.argtypes = [i64, i64]
     lib.gc_batch_step_workspace_bytes.restype = sz
     lib.gc_batch_step.argtypes = [i64, p, p, p, p, i32, p, sz, p]
     lib.gc_copy_segments.argtypes = [i64, p, i64, p]
     lib.gc_version.restype = ctypes.c_char_p
     for name in ("gc_create", "gc_color", "gc_get_stats", "gc_get_round_sizes", "gc_set_option",
-                 "gc_get_option", "gc_get_profile", "gc_destroy", "gc_color_batch", "gc_batch_step"):
+                 "gc_get_option", "gc_get_profile", "gc_destroy", "gc_color_batch", "gc_batch_step",
+                 "gc_color_batch_noalloc"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -198,6 +200,16 @@ def gc_color_batch(num_graphs, voff, eoff, rowptr_local, colidx_local, colors_ou
     _check(load().gc_color_batch(num_graphs, _ptr(voff), _ptr(eoff), _ptr(rowptr_local),
                                  _ptr(colidx_local), _ptr(colors_out), _ptr(rounds_out),
                                  _ptr(workspace), workspace_bytes, _stream(stream)))
+
+
+GC_STATIC_BATCH_MAX_GRAPHS = 65536
+
+
+def gc_color_batch_noalloc(num_graphs, voff, eoff, rowptr_local, colidx_local, colors_out,
+                           rounds_out, stream=None) -> None:
+    _check(load().gc_color_batch_noalloc(num_graphs, _ptr(voff), _ptr(eoff), _ptr(rowptr_local),
+                                         _ptr(colidx_local), _ptr(colors_out), _ptr(rounds_out),
+                                         _stream(stream)))
 
 
 def gc_batch_step_workspace_bytes(num_graphs: int, total_vertices: int) -> int:
