@@ -92,6 +92,7 @@ struct gc_ctx {
   uint8_t* seen = nullptr;    // device, n * kPushColors (push algorithm), allocated on first use
   uint8_t* wide = nullptr;    // device, wide_blocks * kWideColors (push algorithm)
   int64_t wide_blocks = 0;    // blocks allocated in `wide`
+  gc::PushTask* tasks = nullptr;  // device, wide_blocks: pushes queued for the grid-wide pass
   int32_t* widx = nullptr;    // device, n: wide block of each medium/heavy vertex, -1 otherwise
   int32_t* skip = nullptr;    // device, n: final-prefix offset of each row (sorted rows)
   int32_t* part = nullptr;    // device, cus * kMaxBlocksPerCu: per-workgroup round sizes
@@ -225,6 +226,11 @@ static KArgs make_args(const gc_ctx* h, int32_t* colors, int light_max) {
   a.widx = h->widx;
   a.skip = h->skip;
   a.part = h->part;
+  // long rows of wavefront- and workgroup-class winners are pushed by a
+  // grid-wide pass after each detect pass
+  // (not inside the single persistent launch)
+  a.tasks = (a.push && h->mcount + h->hcount > 0 && h->mode != GC_MODE_PERSISTENT) ? h->tasks
+                                                                                   : nullptr;
   a.ctrl = h->ctrl;
   return a;
 }
@@ -284,6 +290,7 @@ static void free_ctx(gc_ctx* h) {
   if (h->dcounts) (void)hipFree(h->dcounts);
   if (h->seen) (void)hipFree(h->seen);
   if (h->wide) (void)hipFree(h->wide);
+  if (h->tasks) (void)hipFree(h->tasks);
   if (h->widx) (void)hipFree(h->widx);
   if (h->skip) (void)hipFree(h->skip);
   if (h->part) (void)hipFree(h->part);
@@ -449,7 +456,7 @@ static bool usable(const Captured& c, int K, int L, int grid, const KArgs& a) {
          b.mlist == a.mlist && b.mcount == a.mcount && b.hlist == a.hlist &&
          b.hcount == a.hcount && b.sorted == a.sorted && b.push == a.push && b.seq == a.seq &&
          b.seen == a.seen && b.flags_by_chunk == a.flags_by_chunk && b.wide == a.wide && b.widx == a.widx && b.skip == a.skip &&
-         b.part == a.part && b.ctrl == a.ctrl;
+         b.part == a.part && b.tasks == a.tasks && b.ctrl == a.ctrl;
 }
 
 static float elapsed(hipEvent_t a, hipEvent_t b) {
@@ -590,6 +597,10 @@ static int color_blocks(gc_ctx* h, int32_t* colors_out, int32_t* user_out, hipSt
       HIPCHECK(h, hipStreamSynchronize(s));
       if (!h->host->flag) break;
       if (h->max_rounds > 0 && r >= h->max_rounds) break;
+      // Lemma 2: at most p rounds (p + 1 as the paper states it)
+      if (r > b.p + 1) return set_err(h, GC_EDEVICE, "round %d > p + 1 = %lld: the p-block "
+                                      "colouring is not converging (internal error)", r,
+                                      (long long)(b.p + 1));
     }
   } else if (h->profile) {
     HIPCHECK(h, hipEventRecord(h->pev[1], s));
@@ -649,9 +660,12 @@ extern "C" int gc_color(gc_handle h, int32_t* colors_out, void* stream) {
       rc = ensure_idle(h);
       if (rc) return rc;
       if (h->wide) (void)hipFree(h->wide);
+      if (h->tasks) (void)hipFree(h->tasks);
       h->wide = nullptr;
+      h->tasks = nullptr;
       h->wide_blocks = 0;
       hipError_t e = hipMalloc((void**)&h->wide, (size_t)blocks * gc::kWideColors);
+      if (e == hipSuccess) e = hipMalloc((void**)&h->tasks, (size_t)blocks * sizeof(gc::PushTask));
       if (e != hipSuccess) return set_err(h, GC_ENOMEM, "wide colour flags: %s", hipGetErrorString(e));
       h->wide_blocks = blocks;
       h->epoch = 0;  // new memory: the next epoch (1) clears every flag
@@ -716,6 +730,11 @@ extern "C" int gc_color(gc_handle h, int32_t* colors_out, void* stream) {
         HIPCHECK(h, hipStreamSynchronize(s));
         if (!h->host->flag) break;
         if (h->max_rounds > 0 && r >= h->max_rounds) break;
+        // every round colours at least the lowest uncoloured vertex (Lemma 2
+        // with one vertex per block), so R <= n: more rounds mean a broken
+        // invariant, reported instead of looping
+        if (r > h->n) return set_err(h, GC_EDEVICE, "round %d > n = %lld: the colouring is not "
+                                     "converging (internal error)", r, (long long)h->n);
         if (mode == GC_MODE_HOST) {
           ++r;
           LCHECK(h, gc::launch_round(a, h->rp64, h->sbytes, L, 0, r, false, grid, s));

@@ -31,6 +31,10 @@ constexpr int kSparseChunk = 32;    // detect: at most this many uncoloured vert
                                     // -> a group of lanes each (at least 2)
 constexpr int kMaxBlocksPerCu = 64; // workgroups per CU of any round kernel (option limit)
 constexpr int kFinishBlocks = 512;  // most workgroups of the finishing pass (one stats pair each)
+constexpr int kDeferRow = 1024;     // a wavefront- or workgroup-class winner with more row entries
+                                    // than this left to push queues them for the grid-wide push pass
+constexpr int kPieceEntries = 1024; // row entries of one piece of that pass: one workgroup,
+                                    // four entries per thread in flight, one step
 constexpr int kFinishHeader = 4;   // its leading output words (see launch_finish)
 constexpr int kFinishWords = kFinishHeader + 2 * kFinishBlocks;
 
@@ -41,8 +45,16 @@ struct alignas(128) Line {
   int32_t pad[31];
 };
 
+// Which degree classes still have uncoloured vertices in a round (1 = yes or
+// not known to be none): a pass skips a class with none.
+struct alignas(128) ClassLine {
+  int32_t light, medium, heavy;
+  int32_t pad[29];
+};
+
 struct Ctrl {
   Line more[3];          // slot r % 3 == 1 when round r has uncoloured vertices
+  ClassLine cls[3];      // slot r % 3: the classes with uncoloured vertices in round r
   Line last_round;       // last round that had uncoloured vertices
   Line round_base;       // first round of the next captured chunk
   Line bar;              // grid barrier arrivals (monotonic within a launch)
@@ -52,7 +64,19 @@ struct Ctrl {
   Line pend;             // round whose per-workgroup counts in KArgs::part are not yet in
                          // trace (0: none)
   Line pend_grid;        // workgroups of that round's detect pass
+  Line tasks;            // 64-bit: push tasks (high half) and their pieces (low half)
+                         // queued by this round's detect pass (KArgs::tasks)
   int32_t trace[kTraceRounds];  // |U_r| at slot r - 1
+};
+
+// A winner's pushes handed to the grid-wide push pass: colour t to the row
+// entries [b, e), cut into pieces first .. first + ceil((e - b) / kPieceEntries) - 1
+// of the pass's piece numbering.
+struct PushTask {
+  int64_t b;
+  int64_t e;
+  int32_t t;
+  int32_t first;
 };
 
 // Arguments of every round kernel.
@@ -88,6 +112,10 @@ struct KArgs {
                           // (sorted rows); zeroed by round 1
   int32_t* part;          // cus * kMaxBlocksPerCu: active vertices of each workgroup of the
                           // last detect pass; the next pass folds them into ctrl->trace
+  PushTask* tasks;        // mcount + hcount: pushes of long rows queued by a detect pass for
+                          // the grid-wide push pass that follows it (push algorithm with
+                          // medium or heavy vertices, not in the persistent kernel; null
+                          // otherwise)
   Ctrl* ctrl;
 };
 

@@ -47,8 +47,9 @@ struct HeavySmem {
   uint32_t bm[kHeavyWindow / 32];
   uint64_t am[4][kWavesPerBlock], cm[4][kWavesPerBlock], pm[4][kWavesPerBlock];  // detect_block_skip
   int first;
-  int active;  // per-block tallies of a detect phase
-  int lost;
+  int wact[kWavesPerBlock];   // per-wave tallies of a detect phase
+  int wlost[kWavesPerBlock];
+  int wcls[kWavesPerBlock];
 };
 
 template <typename RP, typename S>
@@ -190,6 +191,7 @@ __device__ bool detect_block_skip(const int32_t* __restrict__ colidx, const S* _
 struct Tally {
   int active;  // uncoloured vertices this thread's group/wave/block led
   int lost;    // of which lost (detect only)
+  int cls;     // classes of the losers: 1 light, 2 medium, 4 heavy
 };
 
 template <typename RP, typename S, int L, int PHASE>
@@ -215,7 +217,7 @@ __device__ void light_phase(const KArgs& a, long wave_gid, long nwaves, Tally& t
         const int s0 = st[v];
         if (s0 < 0) {
           if (s0 != waiting_state<S>()) st[v] = (S)~s0;
-          else tl.lost += 1;
+          else tl.lost += 1;  // (the class flags are not used by this schedule)
           tl.active += 1;
         }
       }
@@ -304,6 +306,7 @@ __device__ void light_phase(const KArgs& a, long wave_gid, long nwaves, Tally& t
             len = (int)(e - pb);
           }
           tl.lost += olose;
+          tl.cls |= olose;
           tl.active += 1;
         }
       } else if (act) {
@@ -317,6 +320,7 @@ __device__ void light_phase(const KArgs& a, long wave_gid, long nwaves, Tally& t
           len = (int)(e - pb);
         }
         tl.lost += lose;
+        tl.cls |= (int)lose;
         tl.active += 1;
       }
       // every entry is pushed, final neighbours included: their flags are
@@ -358,6 +362,7 @@ __device__ void light_phase(const KArgs& a, long wave_gid, long nwaves, Tally& t
           if (gl == 0) {
             if (!lose) st[vv] = (S)t;
             tl.lost += lose;
+            tl.cls |= (int)lose;
           }
           if (push && !lose) push_colour<RP, S>(a, st, vb, ve, t, epoch, gl, L);
         }
@@ -365,6 +370,21 @@ __device__ void light_phase(const KArgs& a, long wave_gid, long nwaves, Tally& t
       }
     }
   }
+}
+
+// Queue a winner's pushes (colour t to the row entries [b, e)) for the
+// grid-wide push pass.  One 64-bit atomic hands out the task slot (high
+// half) and its first piece (low half), so the tasks' first pieces ascend
+// with their slots.
+__device__ __forceinline__ void queue_push(const KArgs& a, int64_t b, int64_t e, int t) {
+  const uint64_t pieces = (uint64_t)((e - b + kPieceEntries - 1) / kPieceEntries);
+  const uint64_t old = atomicAdd((unsigned long long*)&a.ctrl->tasks, (1ull << 32) | pieces);
+  PushTask x;
+  x.b = b;
+  x.e = e;
+  x.t = t;
+  x.first = (int32_t)(old & 0xffffffffu);
+  a.tasks[old >> 32] = x;
 }
 
 template <typename RP, typename S, int PHASE>
@@ -386,10 +406,18 @@ __device__ void medium_phase(const KArgs& a, long wave_gid, long nwaves, Tally& 
       v = a.mlist[i];
       s = st[v];
       act = s < 0;
-      // with pushed flags only the vertices whose colours 0..31 are all
-      // taken scan their row here (from colour 32); the others took their
-      // colour in the light pass
-      if (PHASE == kSpec && a.push && act) act = taken_colours(a.seen, v, epoch) == ~0u;
+      // with pushed flags a vertex with a free colour among 0..31 takes the
+      // first one here (the light pass, which reads every vertex's flags,
+      // may do the same: it writes the same value, and it is skipped once
+      // no light vertex is left); only the vertices whose colours 0..31 are
+      // all taken scan their row below (from colour 32)
+      if (PHASE == kSpec && a.push && act) {
+        const uint32_t m = taken_colours(a.seen, v, epoch);
+        if (m != ~0u) {
+          st[v] = (S)~__builtin_ctz(~m);
+          act = false;
+        }
+      }
     }
     uint64_t am = __ballot(act);
     while (am) {  // wave-uniform
@@ -429,8 +457,16 @@ __device__ void medium_phase(const KArgs& a, long wave_gid, long nwaves, Tally& 
         if (lane == 0) {
           if (!lose) st[vv] = (S)t;
           tl.lost += lose;
+          tl.cls |= lose ? 2 : 0;
         }
-        if (a.push && !lose) push_colour<RP, S>(a, st, pb, e, t, epoch, lane, kWave);
+        if (a.push && !lose) {
+          if (a.tasks && e - pb > (RP)kDeferRow) {
+            // a long row: the push pass after this one spreads it over the grid
+            if (lane == 0) queue_push(a, pb, e, t);
+          } else {
+            push_colour<RP, S>(a, st, pb, e, t, epoch, lane, kWave);
+          }
+        }
       }
       if (lane == 0) tl.active += 1;
     }
@@ -512,9 +548,13 @@ __device__ void heavy_phase(const KArgs& a, long blk, long nblk, Tally& tl, Heav
   for (long i = blk; i < a.hcount; i += nblk) {
     const int v = a.hlist[i];
     const int s = st[v];
-    const bool skip =
-        PHASE == kSpec && a.push && taken_colours(a.seen, v, a.ctrl->epoch.v) != ~0u;
+    // with pushed flags a vertex with a free colour among 0..31 takes the
+    // first one (as in the medium pass)
+    const uint32_t m =
+        PHASE == kSpec && a.push && s < 0 ? taken_colours(a.seen, v, a.ctrl->epoch.v) : ~0u;
+    const bool skip = m != ~0u;
     __syncthreads();  // the commit below happens after every thread read s
+    if (skip && threadIdx.x == 0) st[v] = (S)~__builtin_ctz(~m);
     if (s >= 0 || skip) continue;  // block-uniform
     const RP b = rp[v], e = rp[v + 1];
     if (PHASE == kSpec && a.seq) {
@@ -560,32 +600,73 @@ __device__ void heavy_phase(const KArgs& a, long blk, long nblk, Tally& tl, Heav
       if (threadIdx.x == 0) {
         if (!lose) st[v] = (S)t;
         tl.lost += lose;
+        tl.cls |= lose ? 4 : 0;
       }
-      if (a.push && !lose) push_colour<RP, S>(a, st, pb, e, t, a.ctrl->epoch.v, threadIdx.x, kBlock);
+      if (a.push && !lose) {
+        if (a.tasks && e - pb > (RP)kDeferRow) {
+          // a hub's long row: its pushes are spread over the whole grid by
+          // the pass that follows, instead of one workgroup walking it
+          if (threadIdx.x == 0) queue_push(a, pb, e, t);
+        } else {
+          push_colour<RP, S>(a, st, pb, e, t, a.ctrl->epoch.v, threadIdx.x, kBlock);
+        }
+      }
     }
     if (threadIdx.x == 0) tl.active += 1;
   }
 }
 
+// Round q's flags start clear; the detect pass of round q - 1 sets them.
+__device__ __forceinline__ void clear_round_flags(const KArgs& a, int q) {
+  a.ctrl->more[q % 3].v = 0;
+  ClassLine& c = a.ctrl->cls[q % 3];
+  c.light = 0;
+  c.medium = 0;
+  c.heavy = 0;
+}
+
 // Detect publishes, per block: whether round r + 1 has work
 // (more[(r+1) % 3]), r as the last non-empty round, and |U_r| in the trace.
 __device__ void publish_detect(const KArgs& a, int r, const Tally& tl, HeavySmem& sm) {
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    sm.active = 0;
-    sm.lost = 0;
+  // per-wave sums by cross-lane reduction, then one slot per wave in LDS
+  // (same-address LDS atomics from every lane used to serialise here)
+  int act = tl.active, lost = tl.lost, cls = tl.cls;
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    act += __shfl_xor(act, off);
+    lost += __shfl_xor(lost, off);
+    cls |= __shfl_xor(cls, off);
+  }
+  const int w = threadIdx.x / kWave;
+  if (lane_id() == 0) {
+    sm.wact[w] = act;
+    sm.wlost[w] = lost;
+    sm.wcls[w] = cls;
   }
   __syncthreads();
-  if (tl.active) atomicAdd(&sm.active, tl.active);
-  if (tl.lost) atomicAdd(&sm.lost, tl.lost);
-  __syncthreads();
   if (threadIdx.x == 0) {
-    if (sm.lost) a.ctrl->more[(r + 1) % 3].v = 1;
-    if (sm.active) a.ctrl->last_round.v = r;
+    act = lost = cls = 0;
+#pragma unroll
+    for (int i = 0; i < kWavesPerBlock; ++i) {
+      act += sm.wact[i];
+      lost += sm.wlost[i];
+      cls |= sm.wcls[i];
+    }
+    if (lost) a.ctrl->more[(r + 1) % 3].v = 1;
+    // the classes that keep uncoloured vertices into round r + 1 (plain
+    // stores of 1 from any block that saw one; only graphs with several
+    // classes read them)
+    if (a.mcount + a.hcount > 0 && a.seq == 0) {
+      ClassLine& c = a.ctrl->cls[(r + 1) % 3];
+      if (cls & 1) c.light = 1;
+      if (cls & 2) c.medium = 1;
+      if (cls & 4) c.heavy = 1;
+    }
+    if (act) a.ctrl->last_round.v = r;
     // the round's size: one count per workgroup with a plain store, folded
     // by the next pass (same-address device atomics from every workgroup
     // would queue up at the end of the pass)
-    a.part[blockIdx.x] = sm.active;
+    a.part[blockIdx.x] = act;
     if (blockIdx.x == 0) {
       a.ctrl->pend.v = r;
       a.ctrl->pend_grid.v = (int)gridDim.x;
@@ -620,13 +701,22 @@ __device__ void fold_trace(const KArgs& a) {
 // after next.
 template <typename RP, typename S, int L, int PHASE>
 __device__ void phase(const KArgs& a, int r, long blk, long nblk, HeavySmem& sm) {
-  Tally tl{0, 0};
-  if (PHASE == kDetect && blk == 0 && threadIdx.x == 0) a.ctrl->more[(r + 2) % 3].v = 0;
-  heavy_phase<RP, S, PHASE>(a, blk, nblk, tl, sm);
+  Tally tl{0, 0, 0};
+  if (PHASE == kDetect && blk == 0 && threadIdx.x == 0) clear_round_flags(a, r + 2);
+  // A degree class with no uncoloured vertex left is skipped (on power-law
+  // graphs the light vertices are all final long before the hubs: walking
+  // their chunks would cost every later pass the same fixed time).  The
+  // id-priority schedule visits every class every round.
+  // A graph of light vertices only needs no flags (its light class is busy
+  // whenever the round is), and reading them would put a dependent load in
+  // front of every pass.
+  const bool mixed = a.mcount + a.hcount > 0 && a.seq == 0;
+  const ClassLine* c = mixed ? &a.ctrl->cls[r % 3] : nullptr;
+  if (a.hcount > 0 && (!mixed || c->heavy)) heavy_phase<RP, S, PHASE>(a, blk, nblk, tl, sm);
   const long wave_gid = blk * kWavesPerBlock + threadIdx.x / kWave;
   const long nwaves = nblk * kWavesPerBlock;
-  medium_phase<RP, S, PHASE>(a, wave_gid, nwaves, tl);
-  light_phase<RP, S, L, PHASE>(a, wave_gid, nwaves, tl);
+  if (a.mcount > 0 && (!mixed || c->medium)) medium_phase<RP, S, PHASE>(a, wave_gid, nwaves, tl);
+  if (!mixed || c->light) light_phase<RP, S, L, PHASE>(a, wave_gid, nwaves, tl);
   if (PHASE == kDetect) publish_detect(a, r, tl, sm);
 }
 
@@ -636,12 +726,59 @@ template <typename RP, typename S, int L, int PHASE>
 __global__ __launch_bounds__(kBlock) void k_phase(KArgs a, int round, int from_base) {
   __shared__ HeavySmem sm;
   const int r = from_base ? a.ctrl->round_base.v + round : round;
-  if (PHASE == kSpec && blockIdx.x == 0) fold_trace(a);
+  if (PHASE == kSpec && blockIdx.x == 0) {
+    fold_trace(a);
+    // the previous round's push pass has run
+    if (threadIdx.x == 0) *(uint64_t*)&a.ctrl->tasks = 0;
+  }
   if (!a.ctrl->more[r % 3].v) {
-    if (PHASE == kDetect && blockIdx.x == 0 && threadIdx.x == 0) a.ctrl->more[(r + 2) % 3].v = 0;
+    if (PHASE == kDetect && blockIdx.x == 0 && threadIdx.x == 0) clear_round_flags(a, r + 2);
     return;
   }
   phase<RP, S, L, PHASE>(a, r, blockIdx.x, gridDim.x, sm);
+}
+
+// The grid-wide push pass after a detect pass: the queued tasks' rows are
+// cut into pieces of kPieceEntries entries, one workgroup per piece (four
+// entries per thread in flight); each entry marks colour t taken for a
+// neighbour that is still uncoloured, as push_colour does.
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_push_tasks(KArgs a) {
+  const uint64_t packed = *(const uint64_t*)&a.ctrl->tasks;
+  const int count = (int)(packed >> 32);
+  const int64_t pieces = (int64_t)(packed & 0xffffffffu);
+  if (count == 0) return;
+  const S* __restrict__ st = (const S*)a.st;
+  const int epoch = a.ctrl->epoch.v;
+  for (int64_t p = blockIdx.x; p < pieces; p += gridDim.x) {  // workgroup-uniform
+    int lo = 0, hi = count - 1;  // the last task whose first piece is <= p
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) / 2;
+      if (a.tasks[mid].first <= p) lo = mid;
+      else hi = mid - 1;
+    }
+    const PushTask x = a.tasks[lo];
+    const int t = x.t;
+    const int64_t k0 = x.b + (p - x.first) * (int64_t)kPieceEntries;
+    const int64_t k1 = k0 + kPieceEntries < x.e ? k0 + kPieceEntries : x.e;
+    for (int64_t k = k0 + threadIdx.x; k < k1; k += 4 * kBlock) {
+      int u[4], sv[4], w[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) u[j] = k + j * kBlock < k1 ? a.colidx[k + j * kBlock] : -1;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        sv[j] = u[j] >= 0 ? (int)st[u[j]] : 0;
+        w[j] = u[j] >= 0 && t >= kPushColors ? a.widx[u[j]] : -1;
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (u[j] < 0 || sv[j] >= 0) continue;
+        if (t < kPushColors) a.seen[flag_index(a, u[j], t)] = (uint8_t)epoch;
+        else if (t < kPushColors + kWideColors && w[j] >= 0)
+          a.wide[(size_t)w[j] * kWideColors + (t - kPushColors)] = (uint8_t)epoch;
+      }
+    }
+  }
 }
 
 // Round 1 in closed form for sorted rows: nothing is final, so every vertex
@@ -653,7 +790,7 @@ __global__ __launch_bounds__(kBlock) void k_round1_sorted(KArgs a) {
   __shared__ HeavySmem sm;
   const RP* __restrict__ rp = (const RP*)a.rowptr;
   S* __restrict__ st = (S*)a.st;
-  Tally tl{0, 0};
+  Tally tl{0, 0, 0};
   const long tid = blockIdx.x * (long)blockDim.x + threadIdx.x;
   const long nth = (long)gridDim.x * blockDim.x;
   for (long v = tid; v < a.n; v += nth) {
@@ -662,9 +799,10 @@ __global__ __launch_bounds__(kBlock) void k_round1_sorted(KArgs a) {
     st[v] = lose ? (S)-1 : (S)0;
     a.skip[v] = 0;
     tl.lost += lose;
+    tl.cls |= lose ? 7 : 0;  // (any class may have lost: the closed form does not tell)
     tl.active += 1;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) a.ctrl->more[0].v = 0;  // (1 + 2) % 3
+  if (blockIdx.x == 0 && threadIdx.x == 0) clear_round_flags(a, 3);
   publish_detect(a, 1, tl, sm);
 }
 
@@ -680,7 +818,7 @@ __global__ __launch_bounds__(kBlock) void k_round1_sorted_push(KArgs a) {
   const RP* __restrict__ rp = (const RP*)a.rowptr;
   S* __restrict__ st = (S*)a.st;
   const int epoch = a.ctrl->epoch.v;
-  Tally tl{0, 0};
+  Tally tl{0, 0, 0};
   const long wave_gid = blockIdx.x * (long)kWavesPerBlock + threadIdx.x / kWave;
   const long nwaves = (long)gridDim.x * kWavesPerBlock;
   const long nchunks = ((long)a.n + kWave - 1) / kWave;
@@ -694,6 +832,7 @@ __global__ __launch_bounds__(kBlock) void k_round1_sorted_push(KArgs a) {
       st[v] = lose ? (S)-1 : (S)0;
       a.skip[v] = 0;
       tl.lost += lose;
+      tl.cls |= lose ? 7 : 0;  // (any class may have lost: the closed form does not tell)
       tl.active += 1;
       if (!lose) {
         pb = b;
@@ -702,7 +841,7 @@ __global__ __launch_bounds__(kBlock) void k_round1_sorted_push(KArgs a) {
     }
     push_flat<RP, S, false>(a, st, pb, len, 0, epoch);
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) a.ctrl->more[0].v = 0;  // (1 + 2) % 3
+  if (blockIdx.x == 0 && threadIdx.x == 0) clear_round_flags(a, 3);
   publish_detect(a, 1, tl, sm);
 }
 
@@ -739,12 +878,19 @@ __global__ void k_init(KArgs a) {
     a.ctrl->more[0].v = 0;
     a.ctrl->more[1].v = a.n > 0;  // round 1 has work iff there are vertices
     a.ctrl->more[2].v = 0;
+    for (int q = 0; q < 3; ++q) {
+      const int on = q == 1 && a.n > 0;  // round 1: every class may have vertices
+      a.ctrl->cls[q].light = on;
+      a.ctrl->cls[q].medium = on;
+      a.ctrl->cls[q].heavy = on;
+    }
     a.ctrl->last_round.v = 0;
     a.ctrl->round_base.v = 2;
     a.ctrl->pend.v = 0;
     a.ctrl->bar.v = 0;
     a.ctrl->abort.v = 0;
     a.ctrl->left.v = 0;
+    *(uint64_t*)&a.ctrl->tasks = 0;
     a.ctrl->epoch.v = a.epoch;
   }
 }
@@ -882,7 +1028,9 @@ __global__ __launch_bounds__(kBlock) void k_persistent(KArgs a, int max_rounds) 
   }
   phase<RP, S, L, kDetect>(a, 1, blockIdx.x, gridDim.x, sm);
   if (!grid_barrier(a.ctrl, epoch)) return;
-  for (int r = 2; max_rounds <= 0 || r <= max_rounds; ++r) {
+  // (r <= n: R <= n by Lemma 2 with one vertex per block; the bound only
+  // keeps a broken invariant from looping forever)
+  for (int r = 2; r <= a.n && (max_rounds <= 0 || r <= max_rounds); ++r) {
     const int more = __hip_atomic_load(&a.ctrl->more[r % 3].v, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
     if (!more) break;  // grid-uniform: read after a barrier, written before it
@@ -989,9 +1137,15 @@ static int launch_round_t(const KArgs& a, int phase_id, int round, bool from_bas
   if (phase_id == kSpec)
     hipLaunchKernelGGL((k_phase<RP, S, L, kSpec>), dim3(grid), dim3(kBlock), 0, s, a, round,
                        (int)from_base);
-  else
+  else {
     hipLaunchKernelGGL((k_phase<RP, S, L, kDetect>), dim3(grid), dim3(kBlock), 0, s, a, round,
                        (int)from_base);
+    if (a.tasks) {
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return (int)e;
+      hipLaunchKernelGGL((k_push_tasks<S>), dim3(grid), dim3(kBlock), 0, s, a);
+    }
+  }
   return (int)hipGetLastError();
 }
 
