@@ -33,6 +33,20 @@ namespace gc {
 constexpr int kBatchBlock = 1024;         // threads per graph workgroup
 constexpr int kBatchLds = 64 * 1024;      // LDS state slice per workgroup (bytes)
 constexpr int kBatchWaves = kBatchBlock / kWave;
+#ifndef GC_BATCH_SPEC_QUADS
+#define GC_BATCH_SPEC_QUADS 4
+#endif
+#ifndef GC_BATCH_ENTRIES_PER_LANE
+#define GC_BATCH_ENTRIES_PER_LANE 16
+#endif
+#ifndef GC_BATCH_MIN_LANES
+#define GC_BATCH_MIN_LANES 1
+#endif
+constexpr int kSpecQuads = GC_BATCH_SPEC_QUADS;  // row quads per lane in flight (speculate)
+// lanes per vertex: the largest power of two from kMinLanes to 16 with at
+// least kEntriesPerLane entries of an average row per lane
+constexpr int kEntriesPerLane = GC_BATCH_ENTRIES_PER_LANE;
+constexpr int kMinLanes = GC_BATCH_MIN_LANES;
 constexpr int kBuckets = 64;
 
 struct BatchCtrl {
@@ -156,15 +170,15 @@ __device__ __forceinline__ int spec_quads(const int32_t* __restrict__ ci, const 
         }
       }
     };
-    for (int i = gl; i < nq; i += 2 * L) {
-      const int4 w0 = r.q[i];
-      if (i + L < nq) {
-        const int4 w1 = r.q[i + L];
-        mark(w0, 4 * i);
-        mark(w1, 4 * (i + L));
-      } else {
-        mark(w0, 4 * i);
-      }
+    for (int i = gl; i < nq; i += kSpecQuads * L) {
+      // kSpecQuads quads per lane in flight, then their gathers
+      int4 w[kSpecQuads];
+#pragma unroll
+      for (int j = 0; j < kSpecQuads; ++j)
+        if (i + j * L < nq) w[j] = r.q[i + j * L];
+#pragma unroll
+      for (int j = 0; j < kSpecQuads; ++j)
+        if (i + j * L < nq) mark(w[j], 4 * (i + j * L));
     }
     for (int off = L / 2; off > 0; off >>= 1) m |= shfl_xor64(m, off);
     if (m != ~0ull) return base + __builtin_ctzll(~m);
@@ -319,7 +333,10 @@ __device__ __forceinline__ int run_graph(const GraphRun& g, S* st, int L, int* l
     }
   }
   bool more = __syncthreads_or(any);
-  while (more && (g.max_rounds <= 0 || r - g.rounds_in < g.max_rounds)) {
+  // (r < n: every round colours the lowest uncoloured vertex, so R <= n;
+  // the bound only stops a broken invariant from spinning forever, and the
+  // graph then reports uncoloured vertices)
+  while (more && r < g.n && (g.max_rounds <= 0 || r - g.rounds_in < g.max_rounds)) {
     ++r;
     graph_pass<S, true>(g, st, skipv, L);
     __syncthreads();
@@ -383,9 +400,8 @@ __global__ __launch_bounds__(kBatchBlock, 8) void k_batch_color(int64_t G, gc_gr
     const int64_t nnz = g.n > 0 ? (int64_t)g.rp[g.n] : 0;
     const double avg = g.n > 0 ? (double)nnz / g.n : 0.0;
     int left = 0, rounds;
-    // lanes per vertex: about two quads (eight entries) of an average row
-    // per lane
-    const int L = avg >= 64.0 ? 16 : avg >= 32.0 ? 8 : avg >= 16.0 ? 4 : 2;
+    int L = kMinLanes;
+    while (L < 16 && 2.0 * L * kEntriesPerLane <= avg) L *= 2;
     rounds = dispatch_state(g, maxdeg, smem, L, &left);
     if (threadIdx.x == 0) {
       d[gi].rounds = rounds;
