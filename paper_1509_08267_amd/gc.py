@@ -232,6 +232,29 @@ def gc_copy_segments(count: int, segs, pieces: int, stream=None) -> None:
 
 # ------------------------------------------------------ convenience ------
 
+def copy_segments_raw(src_ptrs, dst_ptrs, words, device, stream=None):
+    """Copy segment i (words[i] int32 words from device address src_ptrs[i]
+    to dst_ptrs[i]) with one gc_copy_segments launch on `stream`; the
+    addresses are trusted (numpy int64 arrays).  Returns the descriptor
+    tensors, which must stay alive until the stream has run the copy."""
+    words = np.asarray(words, dtype=np.int64)
+    keep = words > 0
+    if not keep.any():
+        return None
+    src = np.asarray(src_ptrs, dtype=np.int64)[keep]
+    dst = np.asarray(dst_ptrs, dtype=np.int64)[keep]
+    words = words[keep]
+    per = (words + COPY_PIECE_WORDS - 1) // COPY_PIECE_WORDS
+    first = np.zeros_like(per)
+    np.cumsum(per[:-1], out=first[1:])
+    desc = np.stack([src, dst, words, first], axis=1)
+    h_desc = torch.from_numpy(np.ascontiguousarray(desc)).pin_memory()
+    with torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext():
+        d_desc = h_desc.to(device, non_blocking=True)
+        gc_copy_segments(int(words.size), d_desc, int(per.sum()), stream)
+    return h_desc, d_desc
+
+
 def copy_segments(pairs, stream=None):
     """Copy each (src, dst) pair of int32 device tensors (src.numel() words
     into the start of dst) with one gc_copy_segments launch on `stream`.
@@ -245,18 +268,8 @@ def copy_segments(pairs, stream=None):
             raise ValueError("copy_segments takes int32 device tensors")
         if d.numel() < s.numel() or not s.is_contiguous() or not d.is_contiguous():
             raise ValueError("copy_segments: destination too small or not contiguous")
-    words = np.array([s.numel() for s, _ in pairs], dtype=np.int64)
-    per = (words + COPY_PIECE_WORDS - 1) // COPY_PIECE_WORDS
-    first = np.concatenate([[0], np.cumsum(per)[:-1]]).astype(np.int64)
-    desc = np.stack([np.array([s.data_ptr() for s, _ in pairs], dtype=np.int64),
-                     np.array([d.data_ptr() for _, d in pairs], dtype=np.int64),
-                     words, first], axis=1)
-    dev = pairs[0][1].device
-    h_desc = torch.from_numpy(np.ascontiguousarray(desc)).pin_memory()
-    with torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext():
-        d_desc = h_desc.to(dev, non_blocking=True)
-        gc_copy_segments(len(pairs), d_desc, int(per.sum()), stream)
-    return h_desc, d_desc
+    return copy_segments_raw([s.data_ptr() for s, _ in pairs], [d.data_ptr() for _, d in pairs],
+                             [s.numel() for s, _ in pairs], pairs[0][1].device, stream)
 
 
 class Graph:

@@ -7,23 +7,27 @@ jobs:
 * admission -- a waiting job is admitted, in arrival order, when a slot is
   free and its footprint (rowptr + colidx + colour/state words) fits in the
   arena (first-fit); its CSR is copied into the arena on a copy stream while
-  the GPU keeps computing (from pinned host memory, or device to device when
-  the request already lives on the GPU), and the compute stream waits for
-  that copy only before the first step that includes the job;
+  the GPU keeps computing (from pinned host memory, or, when the request
+  already lives on the GPU, by one gc_copy_segments launch for all the jobs
+  admitted together), and the compute stream waits for that copy only before
+  the first step that includes the job;
 * step -- one gc_batch_step launch advances every resident job by at most
   `rounds_per_step` rounds (each job keeps its own round count; a job's whole
   state between steps is its colour array), so new jobs start as soon as
   they are admitted instead of waiting for the batch to drain;
-* retirement -- a job whose round had no loser is done: its colours are
-  final, its memory and slot are freed at once and go to waiting jobs.
-
-The resident table is kept host-side in exactly the layout of the
-descriptors gc_batch_step reads, so a step costs one small host-to-device
-copy of the table, one launch, and one copy back.
+* pipelining -- the descriptor table lives on the device and each step
+  updates it in place; a step is queued before the previous one has been
+  waited for, so the host admits, copies and retires while the GPU runs, and
+  blocks only on the oldest of the two steps in flight.  A step's rounds and
+  uncoloured counts come back by an asynchronous copy into pinned memory;
+* retirement -- a job whose round had no loser is done: its completion time
+  is when the host sees the step that finished it; it leaves the table at
+  the next launch, and its memory and slot are reused once the step queued
+  behind it (which still lists it, and leaves its colours unchanged) has run.
 
 Each job's colouring is exactly the one gc_color gives for its graph alone
 (the rounds of a job never depend on the other jobs).  Latency is measured
-from a job's arrival to the end of the step that finished it.
+from a job's arrival to the host seeing the end of the step that finished it.
 """
 from __future__ import annotations
 
@@ -118,6 +122,9 @@ class Job:
     finished_at: float = -1.0
     finished_step: int = -1
     colors: np.ndarray | None = None
+    on_device: bool = False   # both arrays live on the server's device
+    rp_ptr: int = 0           # their device addresses (when on_device)
+    ci_ptr: int = 0
 
     @property
     def latency(self) -> float:
@@ -127,15 +134,29 @@ class Job:
 def _as_int32_tensor(a) -> torch.Tensor:
     if isinstance(a, torch.Tensor):
         t = a if a.dtype == torch.int32 else a.to(torch.int32)
-        t = t.contiguous()
-        if t.device.type == "cpu" and not t.is_pinned():
+        if not t.is_contiguous():
+            t = t.contiguous()
+        if not t.is_cuda and not t.is_pinned():
             t = t.pin_memory()
         return t
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).pin_memory()
 
 
+class _Step:
+    """A launched step: its completion event, the pinned copy of the table it
+    wrote, and the job ids of its table rows in order."""
+
+    def __init__(self, number, event, table_host, row_ids):
+        self.number = number
+        self.event = event
+        self.table_host = table_host
+        self.row_ids = row_ids
+
+
 class Server:
     """Continuous batching of colouring jobs on one device."""
+
+    PIPELINE = 2  # steps in flight
 
     def __init__(self, budget_bytes: int, max_slots: int = 1024, rounds_per_step: int = 4,
                  device=None, keep_colors: bool = True):
@@ -150,16 +171,24 @@ class Server:
         self.keep_colors = keep_colors
         self.compute = torch.cuda.Stream(self.device)
         self.copy = torch.cuda.Stream(self.device)
+        self.readback = torch.cuda.Stream(self.device)
         self.waiting: collections.deque[Job] = collections.deque()
-        self.jobs: list[Job] = []                       # resident, in table order
-        self.table = gc.desc_array([])                  # resident descriptors
+        self.jobs: dict[int, Job] = {}     # admitted and not yet released, by id
+        self.row_ids = np.zeros(0, np.int64)  # job ids of the device table, in row order
+        self.table = None                  # device table (uint8, rows * desc size)
+        self.finished = np.zeros(1024, bool)  # by job id: found finished
+        self.dead = 0                      # finished jobs still in row_ids
+        self.inflight: collections.deque[_Step] = collections.deque()
+        self.free_after_next: list[Job] = []  # finished, still listed by a step in flight
         self.done: dict[int, Job] = {}
         self.steps = 0
         self._next_id = 0
         self._ws = None
-        self._pending_copy = None                       # event of the last admission copy
-        self._pending_desc = None                       # its segment descriptors (device)
+        self._pending_copy = None          # event of the last admission copy
+        self._keep = []                    # staging tensors alive until their copy has run
+        self._resident = 0                 # admitted and not yet finished
         self.clock = time.perf_counter
+        gc.desc_array([])                  # the record layout (gc.DESC_DTYPE)
 
     # -------------------------------------------------------------- API --
     def submit(self, rowptr, colidx, arrival: float | None = None) -> int:
@@ -176,12 +205,18 @@ class Server:
             raise gc.GCError(gc.GC_ETOOBIG, f"job needs {words * 4} bytes, budget is "
                                             f"{self.words * 4}")
         job = Job(self._next_id, rp, ci, self.clock() if arrival is None else arrival, n, nnz, words)
+        if rp.is_cuda and ci.is_cuda and rp.device == self.device and ci.device == self.device:
+            job.on_device = True
+            job.rp_ptr = rp.data_ptr()
+            job.ci_ptr = ci.data_ptr()
         self._next_id += 1
+        if self._next_id > self.finished.size:
+            self.finished = np.concatenate([self.finished, np.zeros(self.finished.size, bool)])
         self.waiting.append(job)
         return job.id
 
     def idle(self) -> bool:
-        return not self.waiting and not self.jobs
+        return not self.waiting and self._resident == 0 and not self.inflight
 
     def result(self, job_id: int) -> Job:
         return self.done[job_id]
@@ -189,7 +224,7 @@ class Server:
     # ---------------------------------------------------------- machinery --
     def _admit(self, now: float):
         new = []
-        while self.waiting and len(self.jobs) + len(new) < self.max_slots:
+        while self.waiting and self._resident + len(new) < self.max_slots:
             job = self.waiting[0]
             if job.arrival > now:
                 break
@@ -200,95 +235,176 @@ class Server:
             job.offset = off
             job.admitted_at = self.clock()
             job.admitted_step = self.steps
+            self.jobs[job.id] = job
             new.append(job)
         if not new:
-            return
+            return new
         # the request tensors may still be being written by work queued on the
         # caller's stream: the copies start after it
         self.copy.wait_stream(torch.cuda.current_stream(self.device))
         with torch.cuda.stream(self.copy):
             # CSR already on the device: every array of the admitted jobs in
-            # one gc_copy_segments launch; host arrays: one copy each
-            staged = []
+            # one gc_copy_segments launch, its descriptors built from the
+            # addresses recorded at submission; host arrays: one copy each
+            dev_jobs = [j for j in new if j.on_device]
+            desc = None
+            if dev_jobs:
+                base = self.arena.data_ptr()
+                off = np.fromiter((j.offset for j in dev_jobs), np.int64, len(dev_jobs))
+                n = np.fromiter((j.n for j in dev_jobs), np.int64, len(dev_jobs))
+                nnz = np.fromiter((j.nnz for j in dev_jobs), np.int64, len(dev_jobs))
+                rpw = (n + 1 + 63) // 64 * 64
+                src = np.empty(2 * len(dev_jobs), np.int64)
+                dst = np.empty_like(src)
+                words = np.empty_like(src)
+                src[0::2] = np.fromiter((j.rp_ptr for j in dev_jobs), np.int64, len(dev_jobs))
+                src[1::2] = np.fromiter((j.ci_ptr for j in dev_jobs), np.int64, len(dev_jobs))
+                dst[0::2] = base + 4 * off
+                dst[1::2] = base + 4 * (off + rpw)
+                words[0::2] = n + 1
+                words[1::2] = nnz
+                desc = gc.copy_segments_raw(src, dst, words, self.device, stream=self.copy)
             for job in new:
+                if job.on_device:
+                    continue
                 rpw = _round64(job.n + 1)
-                rp_dst = self.arena[job.offset:job.offset + job.n + 1]
-                ci_dst = self.arena[job.offset + rpw:job.offset + rpw + job.nnz]
-                for src, dst in ((job.rowptr, rp_dst), (job.colidx, ci_dst)):
-                    if src.numel() == 0:
-                        continue
-                    if src.is_cuda and src.device == self.device:
-                        staged.append((src, dst))
-                    else:
-                        dst.copy_(src, non_blocking=True)
-            self._pending_desc = gc.copy_segments(staged, stream=self.copy)
+                self.arena[job.offset:job.offset + job.n + 1].copy_(job.rowptr, non_blocking=True)
+                if job.nnz:
+                    self.arena[job.offset + rpw:job.offset + rpw + job.nnz].copy_(
+                        job.colidx, non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(self.copy)
+        # descriptors and sources stay referenced until the step that waits
+        # for this copy has been queued behind it
+        self._keep.append((desc, [(j.rowptr, j.colidx) for j in new]))
         self._pending_copy = ev
-        rows = []
-        for job in new:
-            rpw = _round64(job.n + 1)
-            ciw = _round64(max(job.nnz, 1))
-            rows.append((job.offset, job.offset + rpw, job.offset + rpw + ciw, job.n, 0))
-        self.table = np.concatenate([self.table, gc.desc_array(rows)])
-        self.jobs.extend(new)
+        self._resident += len(new)
+        return new
 
-    def step(self) -> int:
-        """Admit what fits, advance every resident job by at most
-        rounds_per_step rounds, retire finished jobs.  Returns the number of
-        jobs finished by this step."""
-        self._admit(self.clock())
-        if not self.jobs:
-            return 0
+    def _launch(self, new):
+        """Queue one step over the table: finished rows dropped, new rows
+        appended, then gc_batch_step in place and the table copied back."""
         with torch.cuda.stream(self.compute):
+            if self.dead:
+                keep = np.nonzero(~self.finished[self.row_ids])[0]
+                self.row_ids = self.row_ids[keep]
+                self.dead = 0
+                if keep.size:
+                    # (pinned source, asynchronous copy: nothing here waits
+                    # for the step in flight)
+                    h = torch.from_numpy(keep.astype(np.int64)).pin_memory()
+                    idx = h.to(self.device, non_blocking=True)
+                    self._keep.append(h)
+                    self.table = self.table.view(-1, gc.DESC_DTYPE.itemsize).index_select(0, idx) \
+                        .reshape(-1)
+                else:
+                    self.table = None
+            if new:
+                k = len(new)
+                off = np.fromiter((j.offset for j in new), np.int64, k)
+                n = np.fromiter((j.n for j in new), np.int64, k)
+                nnz = np.fromiter((j.nnz for j in new), np.int64, k)
+                rpw = (n + 1 + 63) // 64 * 64
+                ciw = (np.maximum(nnz, 1) + 63) // 64 * 64
+                rows = np.zeros(k, gc.DESC_DTYPE)
+                rows["rowptr_off"] = off
+                rows["colidx_off"] = off + rpw
+                rows["color_off"] = off + rpw + ciw
+                rows["n"] = n
+                h = torch.from_numpy(rows.view(np.uint8)).pin_memory()
+                d = h.to(self.device, non_blocking=True)
+                self._keep.append(h)
+                self.table = d if self.table is None else torch.cat([self.table, d])
+                self.row_ids = np.concatenate([self.row_ids,
+                                               np.array([j.id for j in new], np.int64)])
             if self._pending_copy is not None:
                 self.compute.wait_event(self._pending_copy)
                 self._pending_copy = None
-                self._pending_desc = None  # the copy stream has it; the step waits for it
-            d_dev = torch.from_numpy(self.table.view(np.uint8)).to(self.device, non_blocking=False)
-            self._ws = gc.batch_step(d_dev, self.arena, self.arena, self.arena,
+            self._ws = gc.batch_step(self.table, self.arena, self.arena, self.arena,
                                      self.rounds_per_step, workspace=self._ws,
                                      stream=self.compute)
-            back = d_dev.cpu()   # waits for the step
+            host = torch.empty(self.table.numel(), dtype=torch.uint8, pin_memory=True)
+            host.copy_(self.table, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(self.compute)
         self.steps += 1
+        self.inflight.append(_Step(self.steps, ev, host, self.row_ids))
+        self._keep = []  # queued behind the waits above: safe to drop on the host
+
+    def _complete_oldest(self) -> int:
+        st = self.inflight.popleft()
+        st.event.synchronize()
         now = self.clock()
-        table = back.numpy().view(gc.DESC_DTYPE).copy()
-        fin = np.nonzero(table["active"] == 0)[0]
-        if fin.size:
-            if self.keep_colors:
-                spans = [(int(table["color_off"][i]), int(table["n"][i])) for i in fin]
-                idx = torch.from_numpy(np.concatenate(
-                    [np.arange(o, o + n, dtype=np.int64) for o, n in spans] or
-                    [np.zeros(0, np.int64)])).to(self.device)
-                with torch.cuda.stream(self.compute):
-                    flat = self.arena.index_select(0, idx).cpu().numpy()
-                pos = 0
-            for k, i in enumerate(fin):
-                j = self.jobs[i]
-                j.rounds = int(table["rounds"][i])
-                j.finished_at = now
-                j.finished_step = self.steps
-                if self.keep_colors:
-                    j.colors = flat[pos:pos + j.n]
-                    pos += j.n
-                self.alloc.release(j.offset, j.words)
-                j.offset = -1
-                j.rowptr = j.colidx = None
-                self.done[j.id] = j
-            keep = table["active"] != 0
-            self.jobs = [j for j, k in zip(self.jobs, keep) if k]
-            self.table = table[keep]
+        table = st.table_host.numpy().view(gc.DESC_DTYPE)
+        # jobs found finished at the previous completion were still listed by
+        # this step; it has run, so their memory can be reused now
+        self._release(self.free_after_next)
+        self.free_after_next = []
+        ids = st.row_ids
+        rows = np.nonzero((table["active"] == 0) & ~self.finished[ids])[0]
+        finished = []
+        for i in rows:
+            job = self.jobs[int(ids[i])]
+            job.rounds = int(table["rounds"][i])
+            job.finished_at = now
+            job.finished_step = st.number
+            finished.append(job)
+            self.done[job.id] = job
+        if rows.size:
+            self.finished[ids[rows]] = True
+            self.dead += rows.size
+            self._resident -= rows.size
+        # a step queued behind this one still lists them (its write-back leaves
+        # their colours as they are); without one, nothing does
+        if self.inflight:
+            self.free_after_next = finished
         else:
-            self.table = table
-        for j, r in zip(self.jobs, self.table["rounds"]):
-            j.rounds = int(r)
-        return int(fin.size)
+            self._release(finished)
+        return len(finished)
+
+    def _release(self, jobs):
+        if not jobs:
+            return
+        if self.keep_colors:
+            # every step that touched these jobs has run; the read uses its own
+            # stream, so it does not wait for the step in flight
+            h = torch.from_numpy(np.concatenate(
+                [np.arange(j.offset + _round64(j.n + 1) + _round64(max(j.nnz, 1)),
+                           j.offset + _round64(j.n + 1) + _round64(max(j.nnz, 1)) + j.n,
+                           dtype=np.int64) for j in jobs])).pin_memory()
+            with torch.cuda.stream(self.readback):
+                idx = h.to(self.device, non_blocking=True)
+                flat = self.arena.index_select(0, idx).cpu().numpy()
+            pos = 0
+            for j in jobs:
+                j.colors = flat[pos:pos + j.n]
+                pos += j.n
+        for j in jobs:
+            self.alloc.release(j.offset, j.words)
+            j.offset = -1
+            j.rowptr = j.colidx = None
+            del self.jobs[j.id]
+
+    def step(self) -> int:
+        """Admit what fits, queue one step over every resident job (at most
+        rounds_per_step rounds each), and wait for the oldest step in flight
+        once the pipeline is full.  Returns the number of jobs found finished."""
+        new = self._admit(self.clock())
+        finished = 0
+        if self._resident > 0 and (new or self.row_ids.size > self.dead):
+            self._launch(new)
+            while len(self.inflight) >= self.PIPELINE:
+                finished += self._complete_oldest()
+        elif self.inflight:
+            finished += self._complete_oldest()
+        return finished
 
     def run_until_idle(self, max_steps: int = 1_000_000):
         for _ in range(max_steps):
             if self.idle():
                 return
-            if not self.jobs and self.waiting and self.waiting[0].arrival > self.clock():
+            if (self._resident == 0 and not self.inflight and self.waiting
+                    and self.waiting[0].arrival > self.clock()):
                 time.sleep(max(0.0, self.waiting[0].arrival - self.clock()))
             self.step()
         raise RuntimeError("server did not drain")
