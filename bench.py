@@ -58,10 +58,13 @@ def parse():
                    help="keep the library's automatic settings instead of tuning them "
                         "(untimed) on the workload first")
     p.add_argument("--tune-budget", type=float, default=20.0)
+    p.add_argument("--retune", action="store_true",
+                   help="time the autotuner's candidates even when the user cache or the "
+                        "library's shipped tuning table has a setting for this graph class")
     p.add_argument("--order", default="natural", choices=["natural", "largest_first", "random"],
                    help="vertex order (relabelled on the device, seed 0 for random); "
                         "checked against the oracle's colouring in that order")
-    p.add_argument("--rounds-per-step", type=int, default=4,
+    p.add_argument("--rounds-per-step", type=int, default=8,
                    help="served path: rounds each server step advances every resident job")
     p.add_argument("--batch-only", action="store_true",
                    help="batched workload: time the one-launch batch only (no per-graph "
@@ -234,7 +237,7 @@ def graph_record(args, golden, host):
     # (the p-block colouring has none of the tuned knobs but the grid)
     if not args.no_autotune and args.lanes == 0 and args.algorithm != "blocks":
         from paper_1509_08267_amd import autotune
-        res = autotune.tune(G, budget_s=args.tune_budget)
+        res = autotune.tune(G, budget_s=args.tune_budget, use_cache=not args.retune)
         tuned = dict(res.setting, cached=res.cached, measurements=len(res.table),
                      ms_start=None if res.cached else round(res.baseline_seconds * 1e3, 4),
                      ms_best=round(res.seconds * 1e3, 4))

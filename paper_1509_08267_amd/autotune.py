@@ -46,6 +46,12 @@ _OPT_IDS = {"lanes": gc.GC_OPT_LANES, "medium_degree": gc.GC_OPT_MEDIUM_DEGREE,
             "heavy_degree": gc.GC_OPT_HEAVY_DEGREE, "blocks_per_cu": gc.GC_OPT_BLOCKS_PER_CU}
 
 
+# Settings the autotuner chose on the devices it was run on, shipped with the
+# library (same layout as the user cache, read-only): a graph class found
+# here is not tuned again unless the caller asks for it.
+SHIPPED_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
+
+
 def default_cache_path() -> str:
     return os.environ.get("GC_AUTOTUNE_CACHE",
                           os.path.join(os.path.expanduser("~"), ".cache",
@@ -110,15 +116,21 @@ class TuneResult:
 class Cache:
     """JSON file: {device_key: {graph_class: {"setting": {...}, "seconds": t}}}."""
 
-    def __init__(self, path: str | None = None):
+    def __init__(self, path: str | None = None, shipped: str | None = SHIPPED_PATH):
         self.path = path or default_cache_path()
         self.data = {}
+        self.shipped = {}
         if os.path.exists(self.path):
             with open(self.path) as f:
                 self.data = json.load(f)
+        if shipped and os.path.exists(shipped):
+            with open(shipped) as f:
+                self.shipped = json.load(f)
 
     def get(self, dev: str, cls: str):
-        return self.data.get(dev, {}).get(cls)
+        """The user cache's entry, else the shipped one (or None)."""
+        hit = self.data.get(dev, {}).get(cls)
+        return hit if hit is not None else self.shipped.get(dev, {}).get(cls)
 
     def put(self, dev: str, cls: str, setting: dict, seconds: float) -> None:
         self.data.setdefault(dev, {})[cls] = {"setting": setting, "seconds": seconds}

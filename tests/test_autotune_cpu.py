@@ -68,6 +68,19 @@ def test_cache_round_trip(tmp_path):
     assert json.loads(path.read_text())["dev"]["cls2"]["setting"] == {"lanes": 8}
 
 
+def test_shipped_table_is_a_read_only_fallback(tmp_path):
+    shipped = tmp_path / "shipped.json"
+    shipped.write_text(json.dumps({"dev": {"cls": {"setting": {"lanes": 16}, "seconds": 5e-4}}}))
+    c = autotune.Cache(str(tmp_path / "user.json"), shipped=str(shipped))
+    assert c.get("dev", "cls")["setting"] == {"lanes": 16}       # from the shipped table
+    assert c.get("dev", "other") is None
+    c.put("dev", "cls", {"lanes": 4}, 1e-3)                      # the user's entry wins
+    assert autotune.Cache(str(tmp_path / "user.json"), shipped=str(shipped)).get(
+        "dev", "cls")["setting"] == {"lanes": 4}
+    assert json.loads(shipped.read_text())["dev"]["cls"]["setting"] == {"lanes": 16}
+    assert autotune.Cache(str(tmp_path / "none.json"), shipped=None).get("dev", "cls") is None
+
+
 def test_cache_path_from_environment(monkeypatch, tmp_path):
     monkeypatch.setenv("GC_AUTOTUNE_CACHE", str(tmp_path / "x.json"))
     assert autotune.default_cache_path() == str(tmp_path / "x.json")

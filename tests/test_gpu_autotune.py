@@ -29,7 +29,7 @@ def test_tune_keeps_colours_and_caches(mods, tmp_path, name, g, rp64):
     ref = oracle.rsc(g.rowptr, g.colidx)
     rp = torch.from_numpy(g.rowptr.astype(np.int64 if rp64 else np.int32)).cuda()
     ci = torch.from_numpy(g.colidx).cuda()
-    cache = autotune.Cache(str(tmp_path / "tune.json"))
+    cache = autotune.Cache(str(tmp_path / "tune.json"), shipped=None)
     with gc.Graph(rp, ci) as G:
         res = autotune.tune(G, reps=2, budget_s=15.0, cache=cache)
         assert not res.cached
@@ -42,10 +42,10 @@ def test_tune_keeps_colours_and_caches(mods, tmp_path, name, g, rp64):
         assert np.array_equal(out.cpu().numpy(), ref.colors)
         assert r == ref.rounds
         cls = autotune._class_of(G)
-    assert autotune.Cache(cache.path).get(autotune.device_key(), cls) is not None
+    assert autotune.Cache(cache.path, shipped=None).get(autotune.device_key(), cls) is not None
     # a second graph of the same class takes the cached setting without timing
     with gc.Graph(rp, ci) as G2:
-        res2 = autotune.tune(G2, cache=autotune.Cache(cache.path))
+        res2 = autotune.tune(G2, cache=autotune.Cache(cache.path, shipped=None))
         assert res2.cached and res2.setting == res.setting
         out = G2.color()
         G2.stats()
