@@ -227,3 +227,38 @@ def tune(graph: "gc.Graph", *, reps: int = 5, batch: int = 0, budget_s: float = 
     if best_t < float("inf"):
         cache.put(dev, cls, best, best_t)
     return TuneResult(best, best_t, base_t, table, False)
+
+
+def main(argv=None) -> int:
+    """Tune the named synthetic workloads on this device and write the
+    settings in the cache layout (the shipped table is made this way):
+
+        python -m paper_1509_08267_amd.autotune --out tuning.json er_1m_16m ...
+    """
+    import argparse
+
+    import numpy as np
+
+    import graphgen
+    p = argparse.ArgumentParser(description=main.__doc__)
+    p.add_argument("--out", required=True)
+    p.add_argument("--budget", type=float, default=25.0)
+    p.add_argument("workloads", nargs="+")
+    args = p.parse_args(argv)
+    cache = Cache(args.out, shipped=None)
+    for name in args.workloads:
+        g = graphgen.workload(name)
+        rp64 = g.nnz > 2**31 - 1 or name == "rmat22_ef16"
+        rp = torch.from_numpy(g.rowptr.astype(np.int64 if rp64 else np.int32)).cuda()
+        ci = torch.from_numpy(g.colidx).cuda()
+        with gc.Graph(rp, ci) as G:
+            res = tune(G, budget_s=args.budget, cache=cache, use_cache=False)
+            print(f"{name} {_class_of(G)} {res.setting} {res.seconds * 1e3:.4f} ms "
+                  f"(start {res.baseline_seconds * 1e3:.4f} ms)", flush=True)
+        del rp, ci, g
+    return 0
+
+
+if __name__ == "__main__":
+    import sys
+    sys.exit(main())

@@ -351,7 +351,10 @@ __device__ __forceinline__ int run_graph(const GraphRun& g, S* st, int L, int* l
     if (IN_LDS) g.out[v] = s;
     mine += s < 0;
   }
-  if (mine) atomicAdd(&sh_cnt, mine);
+  // (a cross-lane sum first: one LDS atomic per wave, not per thread)
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) mine += __shfl_xor(mine, off);
+  if (lane_id() == 0 && mine) atomicAdd(&sh_cnt, mine);
   __syncthreads();
   *left = sh_cnt;
   __syncthreads();
@@ -394,7 +397,9 @@ __global__ __launch_bounds__(kBatchBlock, 8) void k_batch_color(int64_t G, gc_gr
     g.max_rounds = max_rounds;
     int mx = 0;
     for (int v = threadIdx.x; v < g.n; v += blockDim.x) mx = max(mx, g.rp[v + 1] - g.rp[v]);
-    if (mx) atomicMax(&sh_max, mx);
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) mx = max(mx, __shfl_xor(mx, off));
+    if (lane_id() == 0 && mx) atomicMax(&sh_max, mx);
     __syncthreads();
     const int maxdeg = sh_max;
     const int64_t nnz = g.n > 0 ? (int64_t)g.rp[g.n] : 0;

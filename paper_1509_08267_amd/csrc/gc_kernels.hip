@@ -652,17 +652,20 @@ __device__ void publish_detect(const KArgs& a, int r, const Tally& tl, HeavySmem
       lost += sm.wlost[i];
       cls |= sm.wcls[i];
     }
-    if (lost) a.ctrl->more[(r + 1) % 3].v = 1;
-    // the classes that keep uncoloured vertices into round r + 1 (plain
-    // stores of 1 from any block that saw one; only graphs with several
-    // classes read them)
-    if (a.mcount + a.hcount > 0 && a.seq == 0) {
+    // Flags shared by every block are read before they are written: a
+    // block stores only what it does not already see, so the stores of
+    // some 1,500 blocks to one line do not queue up at the end of the pass.
+    // (Slot (r + 1) % 3 was cleared by the previous detect pass.)
+    if (lost && !a.ctrl->more[(r + 1) % 3].v) a.ctrl->more[(r + 1) % 3].v = 1;
+    // the classes that keep uncoloured vertices into round r + 1 (only
+    // graphs with several classes read them)
+    if (a.mcount + a.hcount > 0 && a.seq == 0 && cls) {
       ClassLine& c = a.ctrl->cls[(r + 1) % 3];
-      if (cls & 1) c.light = 1;
-      if (cls & 2) c.medium = 1;
-      if (cls & 4) c.heavy = 1;
+      if ((cls & 1) && !c.light) c.light = 1;
+      if ((cls & 2) && !c.medium) c.medium = 1;
+      if ((cls & 4) && !c.heavy) c.heavy = 1;
     }
-    if (act) a.ctrl->last_round.v = r;
+    if (act && a.ctrl->last_round.v < r) a.ctrl->last_round.v = r;
     // the round's size: one count per workgroup with a plain store, folded
     // by the next pass (same-address device atomics from every workgroup
     // would queue up at the end of the pass)
