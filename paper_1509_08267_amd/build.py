@@ -15,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgc.so")
-SOURCES = ["gc_api.hip", "gc_kernels.hip", "gc_batch.hip", "gc_blocks.hip", "gc_order.hip"]
+SOURCES = ["gc_api.hip", "gc_kernels.hip", "gc_batch.hip", "gc_blocks.hip", "gc_order.hip",
+           "gc_validate.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

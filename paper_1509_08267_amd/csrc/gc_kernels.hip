@@ -1074,64 +1074,6 @@ __global__ void k_classify(const RP* rowptr, int32_t n, int32_t light_max, int32
   if (threadIdx.x == 0) atomicMax(&counts[2], sh_max);
 }
 
-// CSR checks.  err[0] receives the smallest failing check code (0 = fine),
-// err[1] the vertex (or entry) where one failure of that code was seen:
-//   1 rowptr[0] != 0 or rowptr[n] != m     2 rowptr decreases
-//   3 neighbour id out of range             4 self-loop
-//   5 duplicate entry in a row              6 row not ascending (sorted mode)
-//   7 edge (v, u) without (u, v)
-template <typename RP, bool SORTED>
-__global__ void k_validate(const RP* rowptr, const int32_t* colidx, int32_t n, int64_t m,
-                           int32_t* err) {
-  const long tid = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  const long nth = (long)gridDim.x * blockDim.x;
-  auto fail = [&](int code, long where) {
-    int old = atomicMin(&err[0], code);
-    if (code <= old) err[1] = (int)where;
-  };
-  if (tid == 0 && (rowptr[0] != 0 || (int64_t)rowptr[n] != m)) fail(1, 0);
-  for (long v = tid; v < n; v += nth) {
-    RP b = rowptr[v], e = rowptr[v + 1];
-    if (e < b || b < 0 || (int64_t)e > m) {
-      fail(2, v);
-      continue;
-    }
-    for (RP k = b; k < e; ++k) {
-      int u = colidx[k];
-      if (u < 0 || u >= n) {
-        fail(3, v);
-        continue;
-      }
-      if (u == v) fail(4, v);
-      if (k > b) {
-        int p = colidx[k - 1];
-        if (p == u) fail(5, v);
-        else if (SORTED && p > u) fail(6, v);
-      }
-      if (!SORTED) {
-        for (RP j = b; j < k; ++j)
-          if (colidx[j] == u) fail(5, v);
-      }
-      // symmetry: v must appear in row u
-      RP ub = rowptr[u], ue = rowptr[u + 1];
-      if (ue < ub || ub < 0 || (int64_t)ue > m) continue;  // reported at u
-      bool found = false;
-      if (SORTED) {
-        RP lo = ub, hi = ue;
-        while (lo < hi) {
-          RP mid = lo + (hi - lo) / 2;
-          if (colidx[mid] < v) lo = mid + 1;
-          else hi = mid;
-        }
-        found = lo < ue && colidx[lo] == v;
-      } else {
-        for (RP j = ub; j < ue && !found; ++j) found = colidx[j] == v;
-      }
-      if (!found) fail(7, v);
-    }
-  }
-}
-
 // ------------------------------------------------------ host launchers --
 
 template <typename RP, typename S, int L>
@@ -1318,27 +1260,6 @@ int launch_wide_index(const int32_t* hlist, int32_t hcount, int32_t mcount, int3
   if (hcount <= 0) return 0;
   hipLaunchKernelGGL(k_wide_index, dim3((hcount + kBlock - 1) / kBlock), dim3(kBlock), 0,
                      (hipStream_t)stream, hlist, hcount, mcount, widx);
-  return (int)hipGetLastError();
-}
-
-int launch_validate(const void* rowptr, bool rp64, const int32_t* colidx, int32_t n, int64_t m,
-                    bool sorted, int32_t* err, int grid, void* stream) {
-  hipStream_t s = (hipStream_t)stream;
-  if (rp64) {
-    if (sorted)
-      hipLaunchKernelGGL((k_validate<int64_t, true>), dim3(grid), dim3(kBlock), 0, s,
-                         (const int64_t*)rowptr, colidx, n, m, err);
-    else
-      hipLaunchKernelGGL((k_validate<int64_t, false>), dim3(grid), dim3(kBlock), 0, s,
-                         (const int64_t*)rowptr, colidx, n, m, err);
-  } else {
-    if (sorted)
-      hipLaunchKernelGGL((k_validate<int32_t, true>), dim3(grid), dim3(kBlock), 0, s,
-                         (const int32_t*)rowptr, colidx, n, m, err);
-    else
-      hipLaunchKernelGGL((k_validate<int32_t, false>), dim3(grid), dim3(kBlock), 0, s,
-                         (const int32_t*)rowptr, colidx, n, m, err);
-  }
   return (int)hipGetLastError();
 }
 
