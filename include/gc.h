@@ -296,7 +296,7 @@ int gc_color_batch(int64_t num_graphs, const int64_t *voff, const int64_t *eoff,
  * hipMalloc).
  *
  * The arguments and the result are those of gc_color_batch.  The workspace
- * is a fixed device array inside the library (about 2.9 MB, one per GPU the
+ * is a fixed device array inside the library (about 3.5 MB, one per GPU the
  * library runs on, held until the process ends), so:
  *   - num_graphs may not exceed GC_STATIC_BATCH_MAX_GRAPHS (GC_ETOOBIG);
  *   - calls that overlap in time on one GPU (on different streams, or from

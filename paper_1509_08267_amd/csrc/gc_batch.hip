@@ -13,7 +13,13 @@
 //     colour gather of every round is an LDS read; larger graphs keep an
 //     int32 state in the caller's colour array;
 //   - the rounds are separated by workgroup barriers instead of grid-wide
-//     ones, and each graph stops independently when its round has no loser.
+//     ones, and each graph stops independently when its round has no loser;
+//   - a graph with at least twice a workgroup's fair share of the batch's
+//     work (and enough of it to occupy several workgroups) is coloured by a
+//     team of K workgroups instead: it appears K times in the queue, the K
+//     workgroups that take those entries split its chunks, and its rounds are
+//     separated by a barrier of the team (state in the colour array), so one
+//     large graph no longer holds the whole launch to one workgroup's speed.
 // The state between rounds is the colour array itself (final colours >= 0,
 // ~t for a vertex still being coloured with tentative colour t) plus the
 // round count, which makes a step of a few rounds resumable: gc_batch_step
@@ -48,16 +54,43 @@ constexpr int kSpecQuads = GC_BATCH_SPEC_QUADS;  // row quads per lane in flight
 constexpr int kEntriesPerLane = GC_BATCH_ENTRIES_PER_LANE;
 constexpr int kMinLanes = GC_BATCH_MIN_LANES;
 constexpr int kBuckets = 64;
+constexpr int kMaxTeams = 256;          // graphs coloured by a team, per launch
+constexpr int kMaxExtraTickets = 4096;  // queue entries beyond one per graph
+constexpr int64_t kMinTeamWork = 65536; // work (entries + vertices) per team member
+constexpr long kTeamSpinLimit = 1l << 25;
 
 struct BatchCtrl {
-  int32_t queue;  // next position in `order`
-  int32_t pad[63];
+  int32_t queue;    // next position in `order`
+  int32_t tickets;  // entries of `order`: one per graph, K per team graph
+  int32_t pad[62];
 };
 
-// workspace: [BatchCtrl][order: G int32][descs: G gc_graph_desc (packed API only)]
-__host__ __device__ inline size_t ws_order_off() { return sizeof(BatchCtrl); }
-__host__ __device__ inline size_t ws_descs_off(int64_t G) {
-  return (ws_order_off() + (size_t)G * sizeof(int32_t) + 255) & ~(size_t)255;
+// Control words of one team (one 256-byte line each).
+struct TeamCtrl {
+  int32_t k;        // workgroups in the team
+  int32_t joined;   // ranks handed out
+  uint32_t arrive;  // barrier arrivals, counting up within the launch
+  int32_t lost[3];  // "a vertex lost round r" at index r % 3
+  int32_t left;     // vertices left uncoloured (summed over the team)
+  int32_t maxdeg;   // maximum degree (over the team)
+  int32_t abort;    // a barrier wait exceeded the spin limit
+  int32_t pad[55];
+};
+
+// workspace: [BatchCtrl][teams: kMaxTeams TeamCtrl][order: T int32][slot: T int32]
+//            [gk: G int32][descs: G gc_graph_desc (packed API only)], T = G + kMaxExtraTickets
+__host__ __device__ constexpr size_t ws_teams_off() { return sizeof(BatchCtrl); }
+__host__ __device__ constexpr size_t ws_order_off() {
+  return ws_teams_off() + (size_t)kMaxTeams * sizeof(TeamCtrl);
+}
+__host__ __device__ constexpr size_t ws_slot_off(int64_t G) {
+  return ws_order_off() + (size_t)(G + kMaxExtraTickets) * sizeof(int32_t);
+}
+__host__ __device__ constexpr size_t ws_gk_off(int64_t G) {
+  return ws_slot_off(G) + (size_t)(G + kMaxExtraTickets) * sizeof(int32_t);
+}
+__host__ __device__ constexpr size_t ws_descs_off(int64_t G) {
+  return (ws_gk_off(G) + (size_t)G * sizeof(int32_t) + 255) & ~(size_t)255;
 }
 
 // Descriptors of a packed batch.
@@ -80,19 +113,62 @@ __global__ void k_batch_descs(int64_t G, const int64_t* voff, const int64_t* eof
 
 // Largest-first order: one workgroup buckets the graphs by floor(log2(work))
 // (work = CSR entries + vertices) and writes them out bucket by bucket,
-// largest bucket first.  Also resets the work queue.
+// largest bucket first.  A graph whose work is q >= 2 times a workgroup's
+// fair share (total work / nwg) gets a team of K = min(q, nwg, work /
+// kMinTeamWork) workgroups when K >= 2 and a team slot and K - 1 extra queue
+// entries are left; its K entries are consecutive, with the team slot beside
+// them (-1 for a graph of one workgroup).  Also resets the work queue.
+__device__ __forceinline__ uint64_t batch_work(const gc_graph_desc& x, const int32_t* rowptr_base) {
+  const int64_t nnz = x.n > 0 ? rowptr_base[x.rowptr_off + x.n] : 0;
+  return (uint64_t)nnz + (uint64_t)x.n + 1;
+}
+
 __global__ __launch_bounds__(1024) void k_batch_plan(int64_t G, const gc_graph_desc* d,
                                                      const int32_t* rowptr_base, int32_t* order,
-                                                     BatchCtrl* ctrl) {
+                                                     int32_t* slot, int32_t* gk, TeamCtrl* teams,
+                                                     BatchCtrl* ctrl, int nwg) {
   __shared__ int hist[kBuckets];
   __shared__ int base[kBuckets];
+  __shared__ unsigned long long total;
+  __shared__ int nteams, extra;
   for (int i = threadIdx.x; i < kBuckets; i += blockDim.x) hist[i] = 0;
+  if (threadIdx.x == 0) {
+    total = 0;
+    nteams = 0;
+    extra = 0;
+  }
   __syncthreads();
+  uint64_t mine = 0;
+  for (long g = threadIdx.x; g < G; g += blockDim.x) mine += batch_work(d[g], rowptr_base);
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) mine += shfl_xor64(mine, off);
+  if (lane_id() == 0 && mine) atomicAdd(&total, (unsigned long long)mine);
+  __syncthreads();
+  const uint64_t fair = total / (uint64_t)(nwg > 0 ? nwg : 1) + 1;
   for (long g = threadIdx.x; g < G; g += blockDim.x) {
-    const gc_graph_desc x = d[g];
-    const int64_t nnz = x.n > 0 ? rowptr_base[x.rowptr_off + x.n] : 0;
-    const uint64_t work = (uint64_t)nnz + (uint64_t)x.n + 1;
-    atomicAdd(&hist[63 - __builtin_clzll(work)], 1);
+    const uint64_t w = batch_work(d[g], rowptr_base);
+    uint64_t q = w / fair;
+    if (q > (uint64_t)nwg) q = (uint64_t)nwg;
+    if (q > w / kMinTeamWork) q = w / kMinTeamWork;
+    int k = 1, s = -1;
+    if (q >= 2) {
+      const int ts = atomicAdd(&nteams, 1);
+      const int x = atomicAdd(&extra, (int)q - 1);
+      if (ts < kMaxTeams && x + (int)q - 1 <= kMaxExtraTickets) {
+        k = (int)q;
+        s = ts;
+        TeamCtrl* t = teams + s;
+        t->k = k;
+        t->joined = 0;
+        t->arrive = 0;
+        t->lost[0] = t->lost[1] = t->lost[2] = 0;
+        t->left = 0;
+        t->maxdeg = 0;
+        t->abort = 0;
+      }
+    }
+    gk[g] = k | ((s + 1) << 16);
+    atomicAdd(&hist[63 - __builtin_clzll(w)], k);
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -102,13 +178,17 @@ __global__ __launch_bounds__(1024) void k_batch_plan(int64_t G, const gc_graph_d
       acc += hist[b];
     }
     ctrl->queue = 0;
+    ctrl->tickets = acc;
   }
   __syncthreads();
   for (long g = threadIdx.x; g < G; g += blockDim.x) {
-    const gc_graph_desc x = d[g];
-    const int64_t nnz = x.n > 0 ? rowptr_base[x.rowptr_off + x.n] : 0;
-    const uint64_t work = (uint64_t)nnz + (uint64_t)x.n + 1;
-    order[atomicAdd(&base[63 - __builtin_clzll(work)], 1)] = (int32_t)g;
+    const uint64_t w = batch_work(d[g], rowptr_base);
+    const int k = gk[g] & 0xffff, s = (gk[g] >> 16) - 1;
+    const int pos = atomicAdd(&base[63 - __builtin_clzll(w)], k);
+    for (int j = 0; j < k; ++j) {
+      order[pos + j] = (int32_t)g;
+      slot[pos + j] = s;
+    }
   }
 }
 
@@ -244,11 +324,13 @@ __device__ __forceinline__ bool detect_quads(const int32_t* __restrict__ ci,
 }
 
 // One pass (speculate or detect) of one round over the graph's uncoloured
-// vertices by the whole workgroup: each wavefront walks 64-vertex chunks,
-// ballots the uncoloured ones and hands them to its groups of L lanes.
-// `skipv` (or null) holds each vertex's resume offset for the detect scans.
+// vertices by the whole workgroup (member `rank` of a team of K; 0 of 1
+// alone): each wavefront walks 64-vertex chunks, ballots the uncoloured ones
+// and hands them to its groups of L lanes.  `skipv` (or null) holds each
+// vertex's resume offset for the detect scans.
 template <typename S, bool SPEC>
-__device__ __forceinline__ bool graph_pass(const GraphRun& g, S* st, int32_t* skipv, int L) {
+__device__ __forceinline__ bool graph_pass(const GraphRun& g, S* st, int32_t* skipv, int L,
+                                           int rank = 0, int K = 1) {
   const int lane = lane_id();
   const int gl = lane & (L - 1);
   const int grp = lane / L;
@@ -256,7 +338,7 @@ __device__ __forceinline__ bool graph_pass(const GraphRun& g, S* st, int32_t* sk
   const uint64_t gmask = (L == kWave) ? ~0ull : (((1ull << L) - 1) << (grp * L));
   const int wave = threadIdx.x / kWave;
   bool lost = false;
-  for (int ch = wave; ch * kWave < g.n; ch += kBatchWaves) {
+  for (int ch = rank * kBatchWaves + wave; ch * kWave < g.n; ch += K * kBatchWaves) {
     const int v = ch * kWave + lane;
     bool act = false;
     int s = 0, b = 0, e = 0;
@@ -361,6 +443,106 @@ __device__ __forceinline__ int run_graph(const GraphRun& g, S* st, int L, int* l
   return r;
 }
 
+// Barrier of the K workgroups of a team.  Every member runs: each holds
+// one of the team's K consecutive queue entries, a workgroup takes its next
+// entry only after finishing its graph, and the graphs of earlier entries
+// never wait on later ones, so the members of the earliest unfinished team
+// are all taken (the launch is at most two workgroups per compute unit, all
+// resident).  As the persistent kernel's grid barrier: agent-scope release
+// and acquire around one arrival counter; a wait beyond the spin limit sets
+// the team's abort flag, after which the team's barriers return at once.
+__device__ __forceinline__ bool team_barrier(TeamCtrl* tc, int K, unsigned& phase) {
+  __shared__ int sh_abort;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    ++phase;
+    const unsigned target = phase * (unsigned)K;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_fetch_add(&tc->arrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int ab = __hip_atomic_load(&tc->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    long spins = 0;
+    while (!ab && __hip_atomic_load(&tc->arrive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+                      target) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > kTeamSpinLimit) {
+        __hip_atomic_store(&tc->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ab = 1;
+      } else if ((spins & 1023) == 0) {
+        ab = __hip_atomic_load(&tc->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    sh_abort = ab;
+  }
+  __syncthreads();
+  return sh_abort == 0;
+}
+
+__device__ __forceinline__ int team_flag(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The rounds of one graph by member `rank` of a team of K workgroups, with
+// the state in the graph's colour array: the same rounds as run_graph, each
+// member taking every K-th share of the vertices and chunks, the passes
+// separated by team barriers.  "Some vertex lost round r" is gathered in
+// tc->lost[r % 3]: set before the round's last barrier, read after it by
+// every member (so all leave the loop together), and cleared by member 0 at
+// the start of round r + 3, after every member has read it.  Returns the
+// rounds completed; *left receives the vertices still uncoloured (all of
+// them if a barrier gave up).
+__device__ int run_team(const GraphRun& g, TeamCtrl* tc, int rank, int K, int L, int* left) {
+  __shared__ int sh_cnt;
+  int32_t* const st = g.out;
+  unsigned phase = 0;
+  const int t0 = rank * (int)blockDim.x + (int)threadIdx.x;
+  const int tstride = K * (int)blockDim.x;
+  bool any = false;
+  int mx = 0;
+  int r = g.rounds_in;
+  for (int v = t0; v < g.n; v += tstride) {
+    const int b = g.rp[v], e = g.rp[v + 1];
+    mx = max(mx, e - b);
+    if (r == 0) {  // round 1 in closed form, as run_graph
+      const bool lose = e > b && g.ci[b] < v;
+      st[v] = lose ? -1 : 0;
+      any |= lose;
+    } else {
+      any |= st[v] < 0;
+    }
+  }
+  if (r == 0) r = g.n > 0 ? 1 : 0;
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) mx = max(mx, __shfl_xor(mx, off));
+  if (lane_id() == 0 && mx) atomicMax(&tc->maxdeg, mx);
+  if (__syncthreads_or(any) && threadIdx.x == 0) atomicOr(&tc->lost[r % 3], 1);
+  bool ok = team_barrier(tc, K, phase);
+  bool more = ok && team_flag(&tc->lost[r % 3]) != 0;
+  while (more && r < g.n && (g.max_rounds <= 0 || r - g.rounds_in < g.max_rounds)) {
+    ++r;
+    if (rank == 0 && threadIdx.x == 0)
+      __hip_atomic_store(&tc->lost[r % 3], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    graph_pass<int32_t, true>(g, st, nullptr, L, rank, K);
+    if (!(ok = team_barrier(tc, K, phase))) break;
+    const bool lost = graph_pass<int32_t, false>(g, st, nullptr, L > 4 ? L / 2 : L, rank, K);
+    if (__syncthreads_or(lost) && threadIdx.x == 0) atomicOr(&tc->lost[r % 3], 1);
+    if (!(ok = team_barrier(tc, K, phase))) break;
+    more = team_flag(&tc->lost[r % 3]) != 0;
+  }
+  int mine = 0;
+  for (int v = t0; v < g.n; v += tstride) mine += st[v] < 0;
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) mine += __shfl_xor(mine, off);
+  if (threadIdx.x == 0) sh_cnt = 0;
+  __syncthreads();
+  if (lane_id() == 0 && mine) atomicAdd(&sh_cnt, mine);
+  __syncthreads();
+  if (threadIdx.x == 0 && sh_cnt) atomicAdd(&tc->left, sh_cnt);
+  ok = team_barrier(tc, K, phase) && ok;
+  *left = ok ? team_flag(&tc->left) : g.n;
+  return r;
+}
+
 __device__ __forceinline__ int dispatch_state(const GraphRun& g, int maxdeg, char* smem, int L,
                                               int* left) {
   if (maxdeg <= 127 && g.n <= kBatchLds) return run_graph<int8_t, true>(g, (int8_t*)smem, L, left);
@@ -370,14 +552,16 @@ __device__ __forceinline__ int dispatch_state(const GraphRun& g, int maxdeg, cha
   return run_graph<int32_t, false>(g, g.out, L, left);
 }
 
-__global__ __launch_bounds__(kBatchBlock, 8) void k_batch_color(int64_t G, gc_graph_desc* d,
+__global__ __launch_bounds__(kBatchBlock, 8) void k_batch_color(gc_graph_desc* d,
                                                             const int32_t* rowptr_base,
                                                             const int32_t* colidx_base,
                                                             int32_t* colors_base, int max_rounds,
                                                             const int32_t* order,
+                                                            const int32_t* slot, TeamCtrl* teams,
                                                             BatchCtrl* ctrl) {
   extern __shared__ char smem[];
-  __shared__ int sh_idx, sh_max;
+  __shared__ int sh_idx, sh_max, sh_rank;
+  const int tickets = ctrl->tickets;
   for (;;) {
     if (threadIdx.x == 0) {
       sh_idx = atomicAdd(&ctrl->queue, 1);
@@ -385,8 +569,9 @@ __global__ __launch_bounds__(kBatchBlock, 8) void k_batch_color(int64_t G, gc_gr
     }
     __syncthreads();
     const int idx = sh_idx;
-    if (idx >= G) break;  // workgroup-uniform
+    if (idx >= tickets) break;  // workgroup-uniform
     const int gi = order[idx];
+    const int ts = slot[idx];
     const gc_graph_desc x = d[gi];
     GraphRun g;
     g.rp = rowptr_base + x.rowptr_off;
@@ -395,6 +580,24 @@ __global__ __launch_bounds__(kBatchBlock, 8) void k_batch_color(int64_t G, gc_gr
     g.n = x.n;
     g.rounds_in = x.rounds;
     g.max_rounds = max_rounds;
+    if (ts >= 0) {  // one member of a team (workgroup-uniform)
+      TeamCtrl* tc = teams + ts;
+      if (threadIdx.x == 0) sh_rank = atomicAdd(&tc->joined, 1);
+      __syncthreads();
+      const int rank = sh_rank, K = tc->k;
+      const double avg = g.n > 0 ? (double)g.rp[g.n] / g.n : 0.0;
+      int L = kMinLanes;
+      while (L < 16 && 2.0 * L * kEntriesPerLane <= avg) L *= 2;
+      int left = 0;
+      const int rounds = run_team(g, tc, rank, K, L, &left);
+      if (rank == 0 && threadIdx.x == 0) {
+        d[gi].rounds = rounds;
+        d[gi].active = left;
+        d[gi].max_degree = team_flag(&tc->maxdeg);
+      }
+      __syncthreads();  // sh_idx / sh_rank are rewritten for the next entry
+      continue;
+    }
     int mx = 0;
     for (int v = threadIdx.x; v < g.n; v += blockDim.x) mx = max(mx, g.rp[v + 1] - g.rp[v]);
 #pragma unroll
@@ -423,12 +626,14 @@ __global__ void k_batch_rounds_out(int64_t G, const gc_graph_desc* d, int32_t* r
   for (long g = tid; g < G; g += nth) rounds_out[g] = d[g].rounds;
 }
 
-static int batch_grid(int64_t G) {
+// Two workgroups per compute unit (two 64 KB LDS slices per 160 KB), all
+// resident at once, whatever the number of graphs: a team can use workgroups
+// beyond one per graph.
+static int batch_grid() {
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 1;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 1;
-  const int64_t per_cu = 2;  // two 64 KB LDS slices per 160 KB compute unit
-  return (int)(G < per_cu * cus ? G : per_cu * cus);
+  return 2 * (cus > 0 ? cus : 1);
 }
 
 static int run_batch(int64_t G, gc_graph_desc* d, const int32_t* rpb, const int32_t* cib,
@@ -441,12 +646,17 @@ static int run_batch(int64_t G, gc_graph_desc* d, const int32_t* rpb, const int3
     lds_set = true;
   }
   BatchCtrl* ctrl = (BatchCtrl*)ws;
+  TeamCtrl* teams = (TeamCtrl*)((char*)ws + ws_teams_off());
   int32_t* order = (int32_t*)((char*)ws + ws_order_off());
-  hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(1024), 0, s, G, d, rpb, order, ctrl);
+  int32_t* slot = (int32_t*)((char*)ws + ws_slot_off(G));
+  int32_t* gk = (int32_t*)((char*)ws + ws_gk_off(G));
+  const int grid = batch_grid();
+  hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(1024), 0, s, G, d, rpb, order, slot, gk, teams,
+                     ctrl, grid);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return (int)e;
-  hipLaunchKernelGGL(k_batch_color, dim3(batch_grid(G)), dim3(kBatchBlock), kBatchLds, s, G, d, rpb,
-                     cib, colb, max_rounds, order, ctrl);
+  hipLaunchKernelGGL(k_batch_color, dim3(grid), dim3(kBatchBlock), kBatchLds, s, d, rpb, cib, colb,
+                     max_rounds, order, slot, teams, ctrl);
   return (int)hipGetLastError();
 }
 
@@ -509,8 +719,7 @@ namespace gc {
 // the process ends.
 constexpr int64_t kStaticBatchGraphs = GC_STATIC_BATCH_MAX_GRAPHS;
 constexpr size_t kStaticBatchBytes =
-    ((sizeof(BatchCtrl) + (size_t)kStaticBatchGraphs * sizeof(int32_t) + 255) & ~(size_t)255) +
-    (size_t)kStaticBatchGraphs * sizeof(gc_graph_desc) + 256;
+    ws_descs_off(kStaticBatchGraphs) + (size_t)kStaticBatchGraphs * sizeof(gc_graph_desc) + 256;
 static __device__ __align__(256) uint8_t scratch[kStaticBatchBytes];
 
 // Device address of `scratch` on each device, looked up once per device with
@@ -554,7 +763,7 @@ extern "C" int gc_color_batch_noalloc(int64_t num_graphs, const int64_t* voff, c
 
 extern "C" size_t gc_batch_step_workspace_bytes(int64_t num_graphs, int64_t total_vertices) {
   if (num_graphs < 0 || num_graphs > INT32_MAX || total_vertices < 0) return 0;
-  return ws_order_off() + (size_t)num_graphs * sizeof(int32_t) + 256;
+  return ws_descs_off(num_graphs) + 256;
 }
 
 extern "C" int gc_batch_step(int64_t num_graphs, gc_graph_desc* descs, const int32_t* rowptr_base,

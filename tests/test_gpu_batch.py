@@ -138,6 +138,84 @@ def test_resumable_steps(gc, step_rounds):
     assert steps >= int(np.ceil(ref_rounds.max() / step_rounds))
 
 
+def team_graphs():
+    """A batch in which the large graphs are coloured by teams of
+    workgroups: each has at least twice a workgroup's fair share of the
+    batch's work and 2 x 65,536 units of it (the team size is
+    min(work / fair share, work / 65,536, grid))."""
+    gs = [graphgen.er(60000, 600000, 11), graphgen.er(150000, 900000, 12),
+          graphgen.star(200000, 77)]
+    gs += mixed_graphs()[:20]
+    return gs
+
+
+def team_size(gs, i, grid):
+    work = [int(g.nnz) + g.n + 1 for g in gs]
+    fair = sum(work) // grid + 1
+    return min(work[i] // fair, grid, work[i] // 65536)
+
+
+def test_teams_of_workgroups_match_oracle(gc):
+    gs = team_graphs()
+    grid = 2 * torch.cuda.get_device_properties(0).multi_processor_count
+    assert all(team_size(gs, i, grid) >= 2 for i in range(3))
+    assert all(team_size(gs, i, grid) < 2 for i in range(3, len(gs)))
+    b = pack(gs)
+    colors, rounds = run_batch(gc, b)
+    check_against_oracle(b, colors, rounds)
+    # one graph alone takes every workgroup it can use; a second launch on
+    # the same buffers gives the same bits
+    b1 = pack([gs[1]])
+    c1, r1 = run_batch(gc, b1)
+    assert r1[0] == rounds[1] and np.array_equal(c1, colors[b.voff[1]:b.voff[2]])
+
+
+def test_team_colouring_is_fast(gc):
+    """400,000 vertices and 6 M edges alone in a batch: one workgroup needs
+    tens of milliseconds, a team of ~190 about a millisecond."""
+    import time
+    gcmod = gc
+    g = graphgen.er(400000, 6000000, 13)
+    b = pack([g])
+    args = dev(b)
+    for _ in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        colors, rounds = gcmod.color_batch(*args, voff_host=b.voff, eoff_host=b.eoff)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    ref = oracle.rsc(g.rowptr, g.colidx)
+    assert rounds.cpu().numpy()[0] == ref.rounds
+    assert np.array_equal(colors.cpu().numpy(), ref.colors)
+    print(f"one 400k-vertex graph in a batch: {dt * 1e3:.2f} ms")
+    assert dt < 0.030
+
+
+@pytest.mark.parametrize("step_rounds", [1, 3])
+def test_resumable_steps_with_teams(gc, step_rounds):
+    gs = team_graphs()
+    b = pack(gs)
+    ref_colors, ref_rounds = run_batch(gc, b)
+    voff, eoff, rpl, cil = dev(b)
+    colors = torch.full((int(b.voff[-1]),), 777, dtype=torch.int32, device="cuda")
+    rows = [(int(b.voff[i] + i), int(b.eoff[i]), int(b.voff[i]), gs[i].n, 0)
+            for i in range(len(gs))]
+    descs = torch.from_numpy(gc.desc_array(rows).view(np.uint8)).cuda()
+    steps = 0
+    while True:
+        gc.batch_step(descs, rpl, cil, colors, step_rounds)
+        torch.cuda.synchronize()
+        d = descs.cpu().numpy().view(gc.DESC_DTYPE)
+        steps += 1
+        if not d["active"].any():
+            break
+        assert steps < 10000
+    assert np.array_equal(d["rounds"], ref_rounds)
+    assert np.array_equal(colors.cpu().numpy(), ref_colors)
+    maxdeg = [int(np.diff(g.rowptr).max()) if g.n and g.nnz else 0 for g in gs]
+    assert np.array_equal(d["max_degree"], maxdeg)
+
+
 def test_empty_batch_and_bad_workspace(gc):
     b = pack([])
     colors, rounds = gc.color_batch(*dev(pack([graphgen.path(3)])), voff_host=np.array([0, 3]),
