@@ -14,12 +14,14 @@
 //     int32 state in the caller's colour array;
 //   - the rounds are separated by workgroup barriers instead of grid-wide
 //     ones, and each graph stops independently when its round has no loser;
-//   - a graph with at least twice a workgroup's fair share of the batch's
-//     work (and enough of it to occupy several workgroups) is coloured by a
-//     team of K workgroups instead: it appears K times in the queue, the K
-//     workgroups that take those entries split its chunks, and its rounds are
-//     separated by a barrier of the team (state in the colour array), so one
-//     large graph no longer holds the whole launch to one workgroup's speed.
+//   - a graph with at least a workgroup's fair share of the batch's work
+//     (and enough of it to occupy several workgroups) is coloured by a team
+//     of K workgroups instead: it appears K times in the queue, the K
+//     workgroups that take those entries split its chunks, its rounds are
+//     separated by a barrier of the team, and each member keeps a replica of
+//     the state in LDS, reloaded from the shared colour array after every
+//     barrier; so a large graph no longer holds the whole launch to one
+//     workgroup's speed.
 // The state between rounds is the colour array itself (final colours >= 0,
 // ~t for a vertex still being coloured with tentative colour t) plus the
 // round count, which makes a step of a few rounds resumable: gc_batch_step
@@ -57,6 +59,12 @@ constexpr int kBuckets = 64;
 constexpr int kMaxTeams = 256;          // graphs coloured by a team, per launch
 constexpr int kMaxExtraTickets = 4096;  // queue entries beyond one per graph
 constexpr int64_t kMinTeamWork = 65536; // work (entries + vertices) per team member
+#ifndef GC_BATCH_TEAM_SHARE
+#define GC_BATCH_TEAM_SHARE 20
+#endif
+// a graph of work w gets a team of floor(kTeamShare * w / (10 * fair share))
+// workgroups when that is at least 2
+constexpr uint64_t kTeamShare = GC_BATCH_TEAM_SHARE;
 constexpr long kTeamSpinLimit = 1l << 25;
 
 struct BatchCtrl {
@@ -113,11 +121,13 @@ __global__ void k_batch_descs(int64_t G, const int64_t* voff, const int64_t* eof
 
 // Largest-first order: one workgroup buckets the graphs by floor(log2(work))
 // (work = CSR entries + vertices) and writes them out bucket by bucket,
-// largest bucket first.  A graph whose work is q >= 2 times a workgroup's
-// fair share (total work / nwg) gets a team of K = min(q, nwg, work /
-// kMinTeamWork) workgroups when K >= 2 and a team slot and K - 1 extra queue
-// entries are left; its K entries are consecutive, with the team slot beside
-// them (-1 for a graph of one workgroup).  Also resets the work queue.
+// largest bucket first.  A graph whose work w is at least a workgroup's fair
+// share f (total work / nwg) would alone keep one workgroup busy for the
+// whole launch, and longer under the load of the others: it gets a team of
+// K = min(floor(2 w / f), nwg, w / kMinTeamWork) workgroups when K >= 2 and
+// a team slot and K - 1 extra queue entries are left.  Its K entries are
+// consecutive, with the team slot beside them (-1 for a graph of one
+// workgroup).  Also resets the work queue.
 __device__ __forceinline__ uint64_t batch_work(const gc_graph_desc& x, const int32_t* rowptr_base) {
   const int64_t nnz = x.n > 0 ? rowptr_base[x.rowptr_off + x.n] : 0;
   return (uint64_t)nnz + (uint64_t)x.n + 1;
@@ -147,7 +157,7 @@ __global__ __launch_bounds__(1024) void k_batch_plan(int64_t G, const gc_graph_d
   const uint64_t fair = total / (uint64_t)(nwg > 0 ? nwg : 1) + 1;
   for (long g = threadIdx.x; g < G; g += blockDim.x) {
     const uint64_t w = batch_work(d[g], rowptr_base);
-    uint64_t q = w / fair;
+    uint64_t q = kTeamShare * w / (10 * fair);
     if (q > (uint64_t)nwg) q = (uint64_t)nwg;
     if (q > w / kMinTeamWork) q = w / kMinTeamWork;
     int k = 1, s = -1;
@@ -327,10 +337,11 @@ __device__ __forceinline__ bool detect_quads(const int32_t* __restrict__ ci,
 // vertices by the whole workgroup (member `rank` of a team of K; 0 of 1
 // alone): each wavefront walks 64-vertex chunks, ballots the uncoloured ones
 // and hands them to its groups of L lanes.  `skipv` (or null) holds each
-// vertex's resume offset for the detect scans.
+// vertex's resume offset for the detect scans; `mirror` (or null) receives
+// every state write as well (a team's shared copy).
 template <typename S, bool SPEC>
 __device__ __forceinline__ bool graph_pass(const GraphRun& g, S* st, int32_t* skipv, int L,
-                                           int rank = 0, int K = 1) {
+                                           int rank = 0, int K = 1, int32_t* mirror = nullptr) {
   const int lane = lane_id();
   const int gl = lane & (L - 1);
   const int grp = lane / L;
@@ -364,7 +375,10 @@ __device__ __forceinline__ bool graph_pass(const GraphRun& g, S* st, int32_t* sk
       if (valid) {  // group-uniform
         if (SPEC) {
           const int t = spec_quads<S>(g.ci, st, vb, ve, L, gl);
-          if (gl == 0) st[vv] = (S)~t;
+          if (gl == 0) {
+            st[vv] = (S)~t;
+            if (mirror) mirror[vv] = ~t;
+          }
         } else {
           const int t = ~vs;
           int sk = skipv ? skipv[vv] : 0;
@@ -372,7 +386,10 @@ __device__ __forceinline__ bool graph_pass(const GraphRun& g, S* st, int32_t* sk
           const bool lose = detect_quads<S>(g.ci, st, vb, ve, vv, t, L, gl, gmask, grp * L,
                                             skipv ? &sk : nullptr);
           if (gl == 0) {
-            if (!lose) st[vv] = (S)t;
+            if (!lose) {
+              st[vv] = (S)t;
+              if (mirror) mirror[vv] = t;
+            }
             if (skipv && sk != sk0) skipv[vv] = sk;
             lost |= lose;
           }
@@ -482,24 +499,22 @@ __device__ __forceinline__ int team_flag(const int32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// The rounds of one graph by member `rank` of a team of K workgroups, with
-// the state in the graph's colour array: the same rounds as run_graph, each
-// member taking every K-th share of the vertices and chunks, the passes
-// separated by team barriers.  "Some vertex lost round r" is gathered in
-// tc->lost[r % 3]: set before the round's last barrier, read after it by
-// every member (so all leave the loop together), and cleared by member 0 at
-// the start of round r + 3, after every member has read it.  Returns the
-// rounds completed; *left receives the vertices still uncoloured (all of
-// them if a barrier gave up).
-__device__ int run_team(const GraphRun& g, TeamCtrl* tc, int rank, int K, int L, int* left) {
-  __shared__ int sh_cnt;
+// Start of a team's graph: each member takes every K-th vertex for round 1
+// in closed form (or, on resumption, looks for vertices still uncoloured)
+// and its share of the maximum degree; then the team's first barrier.  The
+// shared state is the graph's colour array (int32).  "Some vertex lost round
+// r" is gathered in tc->lost[r % 3]: set before the round's last barrier,
+// read after it by every member (so all leave the loop together), and
+// cleared by member 0 at the start of round r + 3, after every member has
+// read it.
+__device__ bool team_start(const GraphRun& g, TeamCtrl* tc, int rank, int K, unsigned& phase,
+                           int& r) {
   int32_t* const st = g.out;
-  unsigned phase = 0;
   const int t0 = rank * (int)blockDim.x + (int)threadIdx.x;
   const int tstride = K * (int)blockDim.x;
   bool any = false;
   int mx = 0;
-  int r = g.rounds_in;
+  r = g.rounds_in;
   for (int v = t0; v < g.n; v += tstride) {
     const int b = g.rp[v], e = g.rp[v + 1];
     mx = max(mx, e - b);
@@ -516,21 +531,69 @@ __device__ int run_team(const GraphRun& g, TeamCtrl* tc, int rank, int K, int L,
   for (int off = kWave / 2; off > 0; off >>= 1) mx = max(mx, __shfl_xor(mx, off));
   if (lane_id() == 0 && mx) atomicMax(&tc->maxdeg, mx);
   if (__syncthreads_or(any) && threadIdx.x == 0) atomicOr(&tc->lost[r % 3], 1);
-  bool ok = team_barrier(tc, K, phase);
+  return team_barrier(tc, K, phase);
+}
+
+// The rounds of one graph by member `rank` of a team of K workgroups: the
+// same rounds as run_graph, each member taking every K-th 64-vertex chunk,
+// the passes separated by team barriers.  With IN_LDS every member keeps a
+// replica of the whole state in its LDS slice, reloaded from the shared
+// colour array after each barrier, and writes its vertices to both, so the
+// neighbour gathers stay LDS reads; otherwise the passes work on the shared
+// array.  Returns the rounds completed; *left receives the vertices still
+// uncoloured (all of them if a barrier gave up).
+template <typename S, bool IN_LDS>
+__device__ int team_rounds(const GraphRun& g, S* lds, TeamCtrl* tc, int rank, int K, int L,
+                           unsigned& phase, int r, bool ok, int* left) {
+  __shared__ int sh_cnt;
+  int32_t* const gst = g.out;
+  S* const st = IN_LDS ? lds : (S*)gst;
+  int32_t* const mirror = IN_LDS ? gst : nullptr;
+  // the shared array read as aligned 16-byte quads (as quads_of: every quad
+  // read holds at least one of the graph's entries), four per thread in flight
+  const int lead = (int)(((uintptr_t)gst >> 2) & 3);
+  const int4* const q = (const int4*)(gst - lead);
+  const int nq = (g.n + lead + 3) >> 2;
+  auto reload = [&]() {
+    if (IN_LDS) {
+      for (int i0 = threadIdx.x; i0 < nq; i0 += 4 * blockDim.x) {
+        int4 w[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (i0 + j * (int)blockDim.x < nq) w[j] = q[i0 + j * blockDim.x];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int i = i0 + j * (int)blockDim.x;
+          if (i >= nq) continue;
+          int u[4];
+          unpack(w[j], u);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const int v = 4 * i + k - lead;
+            if (v >= 0 && v < g.n) lds[v] = (S)u[k];
+          }
+        }
+      }
+      __syncthreads();
+    }
+  };
   bool more = ok && team_flag(&tc->lost[r % 3]) != 0;
   while (more && r < g.n && (g.max_rounds <= 0 || r - g.rounds_in < g.max_rounds)) {
     ++r;
     if (rank == 0 && threadIdx.x == 0)
       __hip_atomic_store(&tc->lost[r % 3], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    graph_pass<int32_t, true>(g, st, nullptr, L, rank, K);
+    reload();
+    graph_pass<S, true>(g, st, nullptr, L, rank, K, mirror);
     if (!(ok = team_barrier(tc, K, phase))) break;
-    const bool lost = graph_pass<int32_t, false>(g, st, nullptr, L > 4 ? L / 2 : L, rank, K);
+    reload();
+    const bool lost = graph_pass<S, false>(g, st, nullptr, L > 4 ? L / 2 : L, rank, K, mirror);
     if (__syncthreads_or(lost) && threadIdx.x == 0) atomicOr(&tc->lost[r % 3], 1);
     if (!(ok = team_barrier(tc, K, phase))) break;
     more = team_flag(&tc->lost[r % 3]) != 0;
   }
   int mine = 0;
-  for (int v = t0; v < g.n; v += tstride) mine += st[v] < 0;
+  for (int v = rank * (int)blockDim.x + (int)threadIdx.x; v < g.n; v += K * (int)blockDim.x)
+    mine += gst[v] < 0;
 #pragma unroll
   for (int off = kWave / 2; off > 0; off >>= 1) mine += __shfl_xor(mine, off);
   if (threadIdx.x == 0) sh_cnt = 0;
@@ -541,6 +604,21 @@ __device__ int run_team(const GraphRun& g, TeamCtrl* tc, int rank, int K, int L,
   ok = team_barrier(tc, K, phase) && ok;
   *left = ok ? team_flag(&tc->left) : g.n;
   return r;
+}
+
+// A team member's whole graph: the start, then the rounds with the state
+// placement run_graph would pick (by the team's maximum degree).
+__device__ __forceinline__ int run_team(const GraphRun& g, char* smem, TeamCtrl* tc, int rank, int K, int L,
+                        int* left) {
+  unsigned phase = 0;
+  int r = 0;
+  const bool ok = team_start(g, tc, rank, K, phase, r);
+  const int maxdeg = team_flag(&tc->maxdeg);  // complete: every member added it before the barrier
+  if (maxdeg <= 127 && g.n <= kBatchLds)
+    return team_rounds<int8_t, true>(g, (int8_t*)smem, tc, rank, K, L, phase, r, ok, left);
+  if (maxdeg <= 32767 && 2 * g.n <= kBatchLds)
+    return team_rounds<int16_t, true>(g, (int16_t*)smem, tc, rank, K, L, phase, r, ok, left);
+  return team_rounds<int32_t, false>(g, nullptr, tc, rank, K, L, phase, r, ok, left);
 }
 
 __device__ __forceinline__ int dispatch_state(const GraphRun& g, int maxdeg, char* smem, int L,
@@ -589,7 +667,7 @@ __global__ __launch_bounds__(kBatchBlock, 8) void k_batch_color(gc_graph_desc* d
       int L = kMinLanes;
       while (L < 16 && 2.0 * L * kEntriesPerLane <= avg) L *= 2;
       int left = 0;
-      const int rounds = run_team(g, tc, rank, K, L, &left);
+      const int rounds = run_team(g, smem, tc, rank, K, L, &left);
       if (rank == 0 && threadIdx.x == 0) {
         d[gi].rounds = rounds;
         d[gi].active = left;

@@ -140,9 +140,9 @@ def test_resumable_steps(gc, step_rounds):
 
 def team_graphs():
     """A batch in which the large graphs are coloured by teams of
-    workgroups: each has at least twice a workgroup's fair share of the
-    batch's work and 2 x 65,536 units of it (the team size is
-    min(work / fair share, work / 65,536, grid))."""
+    workgroups: each has at least a workgroup's fair share of the batch's
+    work and 2 x 65,536 units of it (the team size is
+    min(2 work / fair share, work / 65,536, grid))."""
     gs = [graphgen.er(60000, 600000, 11), graphgen.er(150000, 900000, 12),
           graphgen.star(200000, 77)]
     gs += mixed_graphs()[:20]
@@ -152,7 +152,7 @@ def team_graphs():
 def team_size(gs, i, grid):
     work = [int(g.nnz) + g.n + 1 for g in gs]
     fair = sum(work) // grid + 1
-    return min(work[i] // fair, grid, work[i] // 65536)
+    return min(2 * work[i] // fair, grid, work[i] // 65536)
 
 
 def test_teams_of_workgroups_match_oracle(gc):
