@@ -120,7 +120,7 @@ __global__ void k_batch_descs(int64_t G, const int64_t* voff, const int64_t* eof
 }
 
 // Largest-first order: one workgroup buckets the graphs by floor(log2(work))
-// (work = CSR entries + vertices) and writes them out bucket by bucket,
+// (batch_work) and writes them out bucket by bucket,
 // largest bucket first.  A graph whose work w is at least a workgroup's fair
 // share f (total work / nwg) would alone keep one workgroup busy for the
 // whole launch, and longer under the load of the others: it gets a team of
@@ -128,8 +128,14 @@ __global__ void k_batch_descs(int64_t G, const int64_t* voff, const int64_t* eof
 // a team slot and K - 1 extra queue entries are left.  Its K entries are
 // consecutive, with the team slot beside them (-1 for a graph of one
 // workgroup).  Also resets the work queue.
+// The work of a graph: its CSR entries and vertices when fresh; when it
+// resumes from an earlier step (rounds > 0), the vertices it left uncoloured
+// times two more than its average degree, an estimate of what its next
+// rounds visit, so that the order and the teams follow the work left.
 __device__ __forceinline__ uint64_t batch_work(const gc_graph_desc& x, const int32_t* rowptr_base) {
   const int64_t nnz = x.n > 0 ? rowptr_base[x.rowptr_off + x.n] : 0;
+  if (x.rounds > 0 && x.n > 0 && x.active >= 0 && x.active <= x.n)
+    return (uint64_t)x.active * (uint64_t)(nnz / x.n + 2) + 1;
   return (uint64_t)nnz + (uint64_t)x.n + 1;
 }
 

@@ -14,7 +14,14 @@ jobs:
 * step -- one gc_batch_step launch advances every resident job by at most
   `rounds_per_step` rounds (each job keeps its own round count; a job's whole
   state between steps is its colour array), so new jobs start as soon as
-  they are admitted instead of waiting for the batch to drain;
+  they are admitted instead of waiting for the batch to drain.  A step
+  launched while jobs that have arrived are still waiting (for a slot, for
+  arena space, or for this step's admission, which has already happened)
+  runs up to `backlog_rounds_per_step` rounds instead: under a steady stream
+  of arrivals that is nearly every step, and fewer, longer steps carry less
+  per-step overhead, which raises the rate the server sustains; a step with
+  no one waiting keeps the short round count, so an isolated job is
+  returned after fewer rounds of its neighbours' work;
 * pipelining -- the descriptor table lives on the device and each step
   updates it in place; a step is queued before the previous one has been
   waited for, so the host admits, copies and retires while the GPU runs, and
@@ -106,7 +113,7 @@ def job_words(n: int, nnz: int) -> int:
     return _round64(n + 1) + _round64(max(nnz, 1)) + _round64(max(n, 1))
 
 
-@dataclass
+@dataclass(slots=True)
 class Job:
     id: int
     rowptr: torch.Tensor      # int32, pinned host or device
@@ -159,7 +166,7 @@ class Server:
     PIPELINE = 2  # steps in flight
 
     def __init__(self, budget_bytes: int, max_slots: int = 1024, rounds_per_step: int = 4,
-                 device=None, keep_colors: bool = True):
+                 device=None, keep_colors: bool = True, backlog_rounds_per_step: int | None = None):
         if budget_bytes < 4096:
             raise ValueError("budget too small")
         self.device = torch.device(device or "cuda:0")
@@ -168,6 +175,9 @@ class Server:
         self.alloc = ArenaAllocator(self.words)
         self.max_slots = int(max_slots)
         self.rounds_per_step = int(rounds_per_step)
+        self.backlog_rounds_per_step = int(4 * rounds_per_step if backlog_rounds_per_step is None
+                                           else backlog_rounds_per_step)
+        self.backlog_steps = 0             # steps launched with the backlog's round count
         self.keep_colors = keep_colors
         self.compute = torch.cuda.Stream(self.device)
         self.copy = torch.cuda.Stream(self.device)
@@ -214,6 +224,51 @@ class Server:
             self.finished = np.concatenate([self.finished, np.zeros(self.finished.size, bool)])
         self.waiting.append(job)
         return job.id
+
+    def submit_packed(self, voff, eoff, rowptr_local, colidx_local, arrivals) -> range:
+        """Queue every graph of a packed batch already on this device, in the
+        layout of gc_color_batch (graph g: rowptr_local[voff[g] + g ..
+        voff[g + 1] + g], colidx_local[eoff[g] .. eoff[g + 1]]; voff, eoff
+        host arrays), graph g arriving at arrivals[g] (absolute times on the
+        server's clock).  Returns the job ids.  The caller keeps the tensors
+        alive and unchanged until the jobs are admitted."""
+        voff = np.asarray(voff, np.int64)
+        eoff = np.asarray(eoff, np.int64)
+        G = voff.size - 1
+        if not (rowptr_local.is_cuda and colidx_local.is_cuda
+                and rowptr_local.device == self.device and colidx_local.device == self.device
+                and rowptr_local.dtype == torch.int32 and colidx_local.dtype == torch.int32
+                and rowptr_local.is_contiguous() and colidx_local.is_contiguous()):
+            raise ValueError("submit_packed takes contiguous int32 tensors on the server's device")
+        n = np.diff(voff)
+        nnz = np.diff(eoff)
+        if G and (n.min() < 0 or nnz.min() < 0 or voff[-1] + G > rowptr_local.numel()
+                  or eoff[-1] > colidx_local.numel()):
+            raise ValueError("offsets do not fit the packed arrays")
+        words = (n + 1 + 63) // 64 * 64 + (np.maximum(nnz, 1) + 63) // 64 * 64 \
+            + (np.maximum(n, 1) + 63) // 64 * 64
+        if G and words.max() > self.words:
+            raise gc.GCError(gc.GC_ETOOBIG, f"a job needs {int(words.max()) * 4} bytes, budget is "
+                                            f"{self.words * 4}")
+        rp_ptr = rowptr_local.data_ptr() + 4 * (voff[:-1] + np.arange(G))
+        ci_ptr = colidx_local.data_ptr() + 4 * eoff[:-1]
+        arrivals = np.asarray(arrivals, np.float64)
+        first = self._next_id
+        need = first + G
+        if need > self.finished.size:
+            self.finished = np.concatenate([self.finished,
+                                            np.zeros(max(need, 2 * self.finished.size)
+                                                     - self.finished.size, bool)])
+        for g, (ng, eg, wg, a, rpp, cip) in enumerate(zip(n.tolist(), nnz.tolist(), words.tolist(),
+                                                          arrivals.tolist(), rp_ptr.tolist(),
+                                                          ci_ptr.tolist())):
+            job = Job(first + g, None, None, a, ng, eg, wg)
+            job.on_device = True
+            job.rp_ptr = rpp
+            job.ci_ptr = cip
+            self.waiting.append(job)
+        self._next_id = need
+        return range(first, need)
 
     def idle(self) -> bool:
         return not self.waiting and self._resident == 0 and not self.inflight
@@ -320,9 +375,12 @@ class Server:
             if self._pending_copy is not None:
                 self.compute.wait_event(self._pending_copy)
                 self._pending_copy = None
+            # a backlog: jobs that have arrived and were not admitted
+            backlog = bool(self.waiting) and self.waiting[0].arrival <= self.clock()
+            rounds = self.backlog_rounds_per_step if backlog else self.rounds_per_step
+            self.backlog_steps += backlog
             self._ws = gc.batch_step(self.table, self.arena, self.arena, self.arena,
-                                     self.rounds_per_step, workspace=self._ws,
-                                     stream=self.compute)
+                                     rounds, workspace=self._ws, stream=self.compute)
             host = torch.empty(self.table.numel(), dtype=torch.uint8, pin_memory=True)
             host.copy_(self.table, non_blocking=True)
             ev = torch.cuda.Event()
@@ -408,6 +466,28 @@ class Server:
                 time.sleep(max(0.0, self.waiting[0].arrival - self.clock()))
             self.step()
         raise RuntimeError("server did not drain")
+
+    def serve_packed(self, voff, eoff, rowptr_local, colidx_local, arrivals, repeats: int = 1):
+        """serve() for a packed batch already on this device (submit_packed),
+        its graphs submitted `repeats` times over: job r * G + g is graph g,
+        arriving arrivals[r * G + g] seconds after the submission of all the
+        jobs is complete (the schedule is registered first, so its cost does
+        not delay the arrivals).  Returns the finished jobs in job order."""
+        G = len(voff) - 1
+        arrivals = np.asarray(arrivals, np.float64)
+        if arrivals.size != repeats * G:
+            raise ValueError("one arrival per graph and repetition")
+        ids = []
+        for r in range(repeats):
+            ids += list(self.submit_packed(voff, eoff, rowptr_local, colidx_local,
+                                           arrivals[r * G:(r + 1) * G]))
+        t0 = self.clock()
+        first = ids[0] if ids else self._next_id
+        for job in self.waiting:
+            if job.id >= first:
+                job.arrival += t0
+        self.run_until_idle()
+        return [self.done[i] for i in ids]
 
     def serve(self, graphs, arrivals, t0: float | None = None):
         """Submit graphs[i] (objects with .rowptr, .colidx) at time

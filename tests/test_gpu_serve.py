@@ -42,8 +42,10 @@ def test_queueing_midflight_admission_and_parity(serve):
         ref = oracle.rsc(g.rowptr, g.colidx)
         assert j.rounds == ref.rounds
         assert np.array_equal(j.colors, ref.colors)
-    # the budget forced queueing: some job waited for memory or a slot
+    # the budget forced queueing: some job waited for memory or a slot, and
+    # the steps taken while jobs waited ran the backlog's round count
     assert any(j.admitted_step > 0 for j in jobs)
+    assert 0 < srv.backlog_steps < srv.steps
     # continuous batching: some job was admitted at a step where another job,
     # admitted earlier, was still being coloured
     midflight = [j for j in jobs
@@ -159,3 +161,28 @@ def test_device_staged_requests(serve, midflight):
         assert j.rounds == ref.rounds
         assert np.array_equal(j.colors, ref.colors)
     assert srv.alloc.used == 0 and srv.idle()
+
+
+@pytest.mark.parametrize("midflight", [False, True])
+def test_packed_submission(serve, midflight):
+    # a packed batch on the device (the layout of gc_color_batch), submitted
+    # as a whole: every job equals the oracle, under a budget that queues
+    gs = graphs(40, 11)
+    voff = np.concatenate([[0], np.cumsum([g.n for g in gs])]).astype(np.int64)
+    eoff = np.concatenate([[0], np.cumsum([g.nnz for g in gs])]).astype(np.int64)
+    rpl = torch.from_numpy(np.concatenate([g.rowptr.astype(np.int32) for g in gs])).cuda()
+    cil = torch.from_numpy(np.concatenate([g.colidx.astype(np.int32) for g in gs])).cuda()
+    biggest = max(serve.job_words(g.n, g.nnz) for g in gs)
+    srv = serve.Server(budget_bytes=4 * 4 * biggest, max_slots=12, rounds_per_step=3)
+    arrivals = (np.sort(np.random.default_rng(9).uniform(0, 0.03, len(gs))) if midflight
+                else np.zeros(len(gs)))
+    jobs = srv.serve_packed(voff, eoff, rpl, cil, arrivals)
+    for g, j in zip(gs, jobs):
+        ref = oracle.rsc(g.rowptr, g.colidx)
+        assert j.rounds == ref.rounds
+        assert np.array_equal(j.colors, ref.colors)
+    assert srv.alloc.used == 0 and srv.idle()
+    with pytest.raises(ValueError):
+        srv.submit_packed(voff, eoff, rpl.cpu(), cil, np.zeros(len(gs)))
+    with pytest.raises(ValueError):
+        srv.submit_packed(voff, eoff + 5, rpl, cil, np.zeros(len(gs)))
