@@ -14,6 +14,8 @@ roofline     the dominant round kernel (speculate or detect, by measured
 step_counters  the whole colouring's HBM bytes from the committed rocprofv3
              FETCH_SIZE / WRITE_SIZE summary (when it was taken on the same
              kernel source and launch setting) over the measured step time
+other_workloads  (default workload) the 27-point stencil and the R-MAT graph,
+             each colour several times on the default path, with parity
 batched      (default workload) the 4,096-graph batch: one gc_color_batch
              launch, the same graphs through the per-graph path, and the
              continuous-batching server (burst and Poisson arrivals, requests
@@ -71,6 +73,9 @@ def parse():
                         "or served comparison); for profiling runs")
     p.add_argument("--no-batched", action="store_true",
                    help="default workload: leave out the batched block")
+    p.add_argument("--no-other", action="store_true",
+                   help="default workload: leave out the stencil and R-MAT colourings "
+                        "(other_workloads)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 1 GiB device copy three times (scales the "
@@ -719,6 +724,56 @@ def batched_block(args, golden, host, standalone):
     return rec, t_step, steps
 
 
+OTHER_WORKLOADS = (("stencil27_160", 10), ("rmat22_ef16", 5))
+
+
+def other_workloads(goldens):
+    """The other single-graph workloads of the scope table, each on the
+    library's default path with the launch setting the autotuner picks from
+    the shipped table: one warm-up colouring, then `steps` back-to-back
+    colourings timed, with parity of the last timed call's colours and
+    rounds against the oracle's recorded values."""
+    import numpy as np
+    import torch
+
+    import graphgen
+    from paper_1509_08267_amd import autotune, gc
+
+    dev = torch.device("cuda:0")
+    res = {}
+    for wl, steps in OTHER_WORKLOADS:
+        golden = goldens[wl]
+        g = graphgen.workload(wl)
+        if g.sha256() != golden["input_sha256"]:
+            raise SystemExit(f"generated input {wl} does not match the recorded workload")
+        rp64 = g.nnz > 2**31 - 1 or wl == "rmat22_ef16"
+        rp = torch.from_numpy(g.rowptr.astype(np.int64 if rp64 else np.int32)).to(dev)
+        ci = torch.from_numpy(g.colidx).to(dev)
+        out = torch.empty(g.n, dtype=torch.int32, device=dev)
+        with gc.Graph(rp, ci) as G:
+            tuned = autotune.tune(G, budget_s=20.0)
+            G.color(out)
+            G.stats()
+            out.fill_(-7)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                G.color(out)
+            rounds, ncolors = G.stats()
+            torch.cuda.synchronize()
+            t = (time.perf_counter() - t0) / steps
+        got = hashlib.sha256(out.cpu().numpy().astype(np.int32).tobytes()).hexdigest()
+        res[wl] = {"n": g.n, "m": g.m, "steps": steps, "ms_per_colouring": round(t * 1e3, 4),
+                   "GTEPS": round(g.m / t / 1e9, 3), "vertices_per_s": round(g.n / t, 1),
+                   "rounds": rounds, "colors": ncolors,
+                   "parity_last_timed_call": got == golden["colors_sha256"]
+                   and rounds == golden["rounds"],
+                   "setting": dict(tuned.setting, cached=tuned.cached)}
+        del rp, ci, out, g
+        torch.cuda.empty_cache()
+    return res
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -744,6 +799,8 @@ def main():
         print(json.dumps(out), flush=True)
         return
     rec = graph_record(args, goldens[args.workload], host)
+    if args.workload == DEFAULT_WORKLOAD and not args.no_other:
+        rec["other_workloads"] = other_workloads(goldens)
     if args.workload == DEFAULT_WORKLOAD and not args.no_batched:
         brec, _, _ = batched_block(args, goldens[BATCH_WORKLOAD], host, False)
         rec["batched"] = brec
