@@ -40,6 +40,7 @@ from __future__ import annotations
 
 import bisect
 import collections
+import gc as pygc
 import time
 from dataclasses import dataclass
 
@@ -458,14 +459,24 @@ class Server:
         return finished
 
     def run_until_idle(self, max_steps: int = 1_000_000):
-        for _ in range(max_steps):
-            if self.idle():
-                return
-            if (self._resident == 0 and not self.inflight and self.waiting
-                    and self.waiting[0].arrival > self.clock()):
-                time.sleep(max(0.0, self.waiting[0].arrival - self.clock()))
-            self.step()
-        raise RuntimeError("server did not drain")
+        # Python's cyclic garbage collector is paused while the loop runs: a
+        # full collection in a process holding a few hundred thousand objects
+        # stalled the loop for tens of milliseconds (measured), which every
+        # job in flight would wait out; the loop itself creates no cycles
+        was_enabled = pygc.isenabled()
+        pygc.disable()
+        try:
+            for _ in range(max_steps):
+                if self.idle():
+                    return
+                if (self._resident == 0 and not self.inflight and self.waiting
+                        and self.waiting[0].arrival > self.clock()):
+                    time.sleep(max(0.0, self.waiting[0].arrival - self.clock()))
+                self.step()
+            raise RuntimeError("server did not drain")
+        finally:
+            if was_enabled:
+                pygc.enable()
 
     def serve_packed(self, voff, eoff, rowptr_local, colidx_local, arrivals, repeats: int = 1):
         """serve() for a packed batch already on this device (submit_packed),
