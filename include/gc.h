@@ -269,7 +269,10 @@ size_t gc_batch_workspace_bytes(int64_t num_graphs, const int64_t *voff,
                                 const int64_t *eoff);
 
 /*
- * gc_color_batch -- colour every graph of a packed batch.
+ * gc_color_batch -- colour every graph of a packed batch.  A graph whose work
+ * (entries + vertices) is at least 1/(2 x CUs) of the batch's is coloured by
+ * a team of workgroups (up to one per 65,536 units of its work), the others
+ * by one workgroup each; the colours are the same either way.
  *
  *   voff, eoff      device, int64[num_graphs + 1], non-decreasing, from 0
  *   rowptr_local    device, int32, sum(n_g + 1) entries (layout above)
@@ -325,7 +328,11 @@ int gc_color_batch_noalloc(int64_t num_graphs, const int64_t *voff, const int64_
  *   n            vertices of the graph
  *   rounds       in: rounds already done (0 = fresh: the state is
  *                initialised); out: rounds done after the step
- *   active       out: vertices still uncoloured after the step (0 = done)
+ *   active       out: vertices still uncoloured after the step (0 = done);
+ *                in (rounds > 0): the value the previous step left, used
+ *                only to order the step's graphs and size their teams of
+ *                workgroups by the work left (any value gives the same
+ *                colours)
  */
 typedef struct gc_graph_desc {
   int64_t rowptr_off;
