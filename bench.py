@@ -14,8 +14,9 @@ roofline     the dominant round kernel (speculate or detect, by measured
 step_counters  the whole colouring's HBM bytes from the committed rocprofv3
              FETCH_SIZE / WRITE_SIZE summary (when it was taken on the same
              kernel source and launch setting) over the measured step time
-other_workloads  (default workload) the 27-point stencil and the R-MAT graph,
-             each colour several times on the default path, with parity
+other_workloads  (default workload) the small ER graph, the 27-point stencil
+             and the R-MAT graph, each coloured several times on the default
+             path, with parity
 batched      (default workload) the 4,096-graph batch: one gc_color_batch
              launch, the same graphs through the per-graph path, and the
              continuous-batching server (burst and Poisson arrivals, requests
@@ -74,8 +75,8 @@ def parse():
     p.add_argument("--no-batched", action="store_true",
                    help="default workload: leave out the batched block")
     p.add_argument("--no-other", action="store_true",
-                   help="default workload: leave out the stencil and R-MAT colourings "
-                        "(other_workloads)")
+                   help="default workload: leave out the small ER, stencil and R-MAT "
+                        "colourings (other_workloads)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 1 GiB device copy three times (scales the "
@@ -724,7 +725,7 @@ def batched_block(args, golden, host, standalone):
     return rec, t_step, steps
 
 
-OTHER_WORKLOADS = (("stencil27_160", 10), ("rmat22_ef16", 5))
+OTHER_WORKLOADS = (("er_10k_100k", 50), ("stencil27_160", 10), ("rmat22_ef16", 5))
 
 
 def other_workloads(goldens):
