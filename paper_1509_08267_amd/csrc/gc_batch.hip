@@ -42,10 +42,10 @@ constexpr int kBatchBlock = 1024;         // threads per graph workgroup
 constexpr int kBatchLds = 64 * 1024;      // LDS state slice per workgroup (bytes)
 constexpr int kBatchWaves = kBatchBlock / kWave;
 #ifndef GC_BATCH_SPEC_QUADS
-#define GC_BATCH_SPEC_QUADS 4
+#define GC_BATCH_SPEC_QUADS 3
 #endif
 #ifndef GC_BATCH_ENTRIES_PER_LANE
-#define GC_BATCH_ENTRIES_PER_LANE 16
+#define GC_BATCH_ENTRIES_PER_LANE 12
 #endif
 #ifndef GC_BATCH_MIN_LANES
 #define GC_BATCH_MIN_LANES 1
@@ -243,7 +243,7 @@ __device__ __forceinline__ void unpack(const int4 w, int* u) {
 }
 
 // Least colour not final on any neighbour of the row [b, e), by a group of L
-// lanes (gl = lane in group) with 16-byte loads, two quads per lane in
+// lanes (gl = lane in group) with 16-byte loads, kSpecQuads quads per lane in
 // flight.  Every lane returns the result.
 template <typename S>
 __device__ __forceinline__ int spec_quads(const int32_t* __restrict__ ci, const S* __restrict__ st,
