@@ -232,11 +232,17 @@ def gc_copy_segments(count: int, segs, pieces: int, stream=None) -> None:
 
 # ------------------------------------------------------ convenience ------
 
-def copy_segments_raw(src_ptrs, dst_ptrs, words, device, stream=None):
+def copy_segments_raw(src_ptrs, dst_ptrs, words, device, stream=None, host_buf=None,
+                      dev_buf=None):
     """Copy segment i (words[i] int32 words from device address src_ptrs[i]
     to dst_ptrs[i]) with one gc_copy_segments launch on `stream`; the
-    addresses are trusted (numpy int64 arrays).  Returns the descriptor
-    tensors, which must stay alive until the stream has run the copy."""
+    addresses are trusted (numpy int64 arrays).  `host_buf` (optional) is a
+    pinned int64 tensor of at least 4 entries per segment that stages the
+    descriptors instead of a new pinned allocation; the caller must not
+    rewrite it before the stream has run the copy.  `dev_buf` (optional) is
+    the same for the device copy of the descriptors (a buffer used only on
+    `stream` can be reused by every call).  Returns the descriptor tensors,
+    which must stay alive until the stream has run the copy."""
     words = np.asarray(words, dtype=np.int64)
     keep = words > 0
     if not keep.any():
@@ -248,9 +254,17 @@ def copy_segments_raw(src_ptrs, dst_ptrs, words, device, stream=None):
     first = np.zeros_like(per)
     np.cumsum(per[:-1], out=first[1:])
     desc = np.stack([src, dst, words, first], axis=1)
-    h_desc = torch.from_numpy(np.ascontiguousarray(desc)).pin_memory()
+    if host_buf is not None and host_buf.numel() >= desc.size:
+        h_desc = host_buf[:desc.size].view(-1, 4)
+        h_desc.numpy()[:] = desc
+    else:
+        h_desc = torch.from_numpy(np.ascontiguousarray(desc)).pin_memory()
     with torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext():
-        d_desc = h_desc.to(device, non_blocking=True)
+        if dev_buf is not None and dev_buf.numel() >= desc.size:
+            d_desc = dev_buf[:desc.size].view(-1, 4)
+            d_desc.copy_(h_desc, non_blocking=True)
+        else:
+            d_desc = h_desc.to(device, non_blocking=True)
         gc_copy_segments(int(words.size), d_desc, int(per.sum()), stream)
     return h_desc, d_desc
 

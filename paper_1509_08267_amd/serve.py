@@ -194,12 +194,41 @@ class Server:
         self.done: dict[int, Job] = {}
         self.steps = 0
         self._next_id = 0
-        self._ws = None
         self._pending_copy = None          # event of the last admission copy
         self._keep = []                    # staging tensors alive until their copy has run
         self._resident = 0                 # admitted and not yet finished
         self.clock = time.perf_counter
         gc.desc_array([])                  # the record layout (gc.DESC_DTYPE)
+        # Pinned host staging, allocated once: a ring of PIPELINE + 1 sets,
+        # set k used by the steps numbered k mod (PIPELINE + 1).  A set is
+        # rewritten only when the step that used it last has completed (the
+        # loop waits for step s - 1 before queueing step s + 1).  Pinned
+        # allocations inside the loop went to the system allocator whenever a
+        # new size appeared, and one took 147 ms (measured).
+        ring = self.PIPELINE + 1
+        rec = gc.DESC_DTYPE.itemsize
+        self._pin_table = [torch.empty(self.max_slots * rec, dtype=torch.uint8, pin_memory=True)
+                           for _ in range(ring)]
+        self._pin_rows = [torch.empty(self.max_slots * rec, dtype=torch.uint8, pin_memory=True)
+                          for _ in range(ring)]
+        self._pin_keep = [torch.empty(self.max_slots, dtype=torch.int64, pin_memory=True)
+                          for _ in range(ring)]
+        self._pin_desc = [torch.empty(2 * self.max_slots * 4, dtype=torch.int64, pin_memory=True)
+                          for _ in range(ring)]
+        # Device buffers, allocated once as well (a new size class inside the
+        # loop reached the device allocator, and one step's set-up took 64 ms,
+        # measured): the descriptor table in one of two buffers (a step's
+        # dropped rows are gathered into the other; both are used only on
+        # the compute stream, in order), the gather's indices, the copy
+        # descriptors (used only on the copy stream) and the step workspace.
+        self._dtab = [torch.empty(self.max_slots * rec, dtype=torch.uint8, device=self.device)
+                      for _ in range(2)]
+        self._dcur = 0                     # the buffer holding the table
+        self._rows = 0                     # rows of the table
+        self._didx = torch.empty(self.max_slots, dtype=torch.int64, device=self.device)
+        self._ddesc = torch.empty(2 * self.max_slots * 4, dtype=torch.int64, device=self.device)
+        self._ws = torch.empty(max(gc.gc_batch_step_workspace_bytes(self.max_slots, 0), 1),
+                               dtype=torch.uint8, device=self.device)
 
     # -------------------------------------------------------------- API --
     def submit(self, rowptr, colidx, arrival: float | None = None) -> int:
@@ -319,7 +348,9 @@ class Server:
                 dst[1::2] = base + 4 * (off + rpw)
                 words[0::2] = n + 1
                 words[1::2] = nnz
-                desc = gc.copy_segments_raw(src, dst, words, self.device, stream=self.copy)
+                desc = gc.copy_segments_raw(src, dst, words, self.device, stream=self.copy,
+                                            host_buf=self._pin_desc[self.steps % len(self._pin_desc)],
+                                            dev_buf=self._ddesc)
             for job in new:
                 if job.on_device:
                     continue
@@ -340,6 +371,8 @@ class Server:
     def _launch(self, new):
         """Queue one step over the table: finished rows dropped, new rows
         appended, then gc_batch_step in place and the table copied back."""
+        slot = self.steps % len(self._pin_table)
+        rec = gc.DESC_DTYPE.itemsize
         with torch.cuda.stream(self.compute):
             if self.dead:
                 keep = np.nonzero(~self.finished[self.row_ids])[0]
@@ -348,13 +381,15 @@ class Server:
                 if keep.size:
                     # (pinned source, asynchronous copy: nothing here waits
                     # for the step in flight)
-                    h = torch.from_numpy(keep.astype(np.int64)).pin_memory()
-                    idx = h.to(self.device, non_blocking=True)
-                    self._keep.append(h)
-                    self.table = self.table.view(-1, gc.DESC_DTYPE.itemsize).index_select(0, idx) \
-                        .reshape(-1)
-                else:
-                    self.table = None
+                    h = self._pin_keep[slot][:keep.size]
+                    h.numpy()[:] = keep
+                    self._didx[:keep.size].copy_(h, non_blocking=True)
+                    cur = self._dtab[self._dcur].view(self.max_slots, rec)
+                    nxt = self._dtab[1 - self._dcur].view(self.max_slots, rec)
+                    torch.index_select(cur[:self._rows], 0, self._didx[:keep.size],
+                                       out=nxt[:keep.size])
+                    self._dcur = 1 - self._dcur
+                self._rows = int(keep.size)
             if new:
                 k = len(new)
                 off = np.fromiter((j.offset for j in new), np.int64, k)
@@ -367,12 +402,14 @@ class Server:
                 rows["colidx_off"] = off + rpw
                 rows["color_off"] = off + rpw + ciw
                 rows["n"] = n
-                h = torch.from_numpy(rows.view(np.uint8)).pin_memory()
-                d = h.to(self.device, non_blocking=True)
-                self._keep.append(h)
-                self.table = d if self.table is None else torch.cat([self.table, d])
+                h = self._pin_rows[slot][:rows.nbytes]
+                h.numpy()[:] = rows.view(np.uint8)
+                dst = self._dtab[self._dcur].view(self.max_slots, rec)[self._rows:self._rows + k]
+                dst.view(-1).copy_(h, non_blocking=True)
+                self._rows += k
                 self.row_ids = np.concatenate([self.row_ids,
                                                np.array([j.id for j in new], np.int64)])
+            self.table = self._dtab[self._dcur][:self._rows * rec]
             if self._pending_copy is not None:
                 self.compute.wait_event(self._pending_copy)
                 self._pending_copy = None
@@ -382,7 +419,7 @@ class Server:
             self.backlog_steps += backlog
             self._ws = gc.batch_step(self.table, self.arena, self.arena, self.arena,
                                      rounds, workspace=self._ws, stream=self.compute)
-            host = torch.empty(self.table.numel(), dtype=torch.uint8, pin_memory=True)
+            host = self._pin_table[slot][:self.table.numel()]
             host.copy_(self.table, non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(self.compute)
