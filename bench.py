@@ -360,46 +360,60 @@ def graph_record(args, golden, host):
         sizes = golden["round_sizes"]
         scan2 = golden["sum_active_scan"] - (sizes[1] if len(sizes) > 1 else 0)
         push_rows = golden["push_rows_after_round1"]
-    per_vertex = 2 * rp_b + 2 * sbytes
-    if algo == "push":
-        spec_bytes = verts2 * (32 + 2 * sbytes)
-    else:
-        spec_bytes = visits2 * (4 + sbytes) + verts2 * per_vertex
-    det_bytes = scan2 * (4 + sbytes) + verts2 * per_vertex
-    if algo == "push":
-        det_bytes += push_rows * (4 + sbytes) \
-            + golden["push_useful_after_round1"]
-    if algo == "seq":
-        # pick (speculate kernel), rounds 2..R: per visit the rowptr pair and
-        # the vertex's state; per waiting visit at least one lower-neighbour
-        # entry and its state; per vertex coloured, its row once (entry +
-        # state gather) and the state write.  Commit (detect kernel): per
-        # visit a state read, per vertex coloured a state write.
-        sv = golden["seq_visits_after_round1"]
-        sc = golden["seq_coloured_after_round1"]
-        spec_bytes = (sv * (2 * rp_b + sbytes) + golden["seq_waiting_visits_after_round1"]
-                      * (4 + sbytes) + golden["seq_rows_after_round1"] * (4 + sbytes)
-                      + sc * sbytes)
-        det_bytes = sv * sbytes + sc * sbytes
+
+    def alg_bytes(sw):
+        """(speculate, detect) bytes per colouring with each state access
+        priced at sw bytes."""
+        per_vertex = 2 * rp_b + 2 * sw
+        if algo == "push":
+            spec_b = verts2 * (32 + 2 * sw)
+        else:
+            spec_b = visits2 * (4 + sw) + verts2 * per_vertex
+        det_b = scan2 * (4 + sw) + verts2 * per_vertex
+        if algo == "push":
+            det_b += push_rows * (4 + sw) + golden["push_useful_after_round1"]
+        if algo == "seq":
+            # pick (speculate kernel), rounds 2..R: per visit the rowptr pair
+            # and the vertex's state; per waiting visit at least one
+            # lower-neighbour entry and its state; per vertex coloured, its row
+            # once (entry + state gather) and the state write.  Commit (detect
+            # kernel): per visit a state read, per vertex coloured a state
+            # write.
+            sv = golden["seq_visits_after_round1"]
+            sc = golden["seq_coloured_after_round1"]
+            spec_b = (sv * (2 * rp_b + sw) + golden["seq_waiting_visits_after_round1"]
+                      * (4 + sw) + golden["seq_rows_after_round1"] * (4 + sw) + sc * sw)
+            det_b = sv * sw + sc * sw
+        if algo == "blocks":
+            # phase 1 ("speculate"): per pending vertex its rowptr pair, todo
+            # byte and colour write, per row entry the neighbour id and its
+            # slot or colour; phase 2 ("detect"): the same reads, per entry
+            # also the slot write (entries whose neighbour is in another
+            # block: all but ~0.2% at p = 16384), per pending vertex the todo
+            # write
+            sa, sd = golden["blocks_sum_active"], golden["blocks_sum_active_deg"]
+            spec_b = sd * 8 + sa * (2 * rp_b + 1 + 4)
+            det_b = sd * 12 + sa * (2 * rp_b + 1 + 4 + 1)
+        return spec_b, det_b
+
+    # The per-unit figures price every state access at the scope table's
+    # 4-byte colour word (the algorithm's state; the kernels keep it in 1 or
+    # 2 bytes where the colours fit, an implementation saving reported beside
+    # it as the "_at_state_width" figures).
+    spec_bytes, det_bytes = alg_bytes(4)
+    spec_bytes_sw, det_bytes_sw = alg_bytes(sbytes)
     # rounds whose kernels are timed per colouring (round 1 has its own launch
     # except in the p-block colouring)
     timed_rounds = rounds if algo == "blocks" else rounds - 1
-    if algo == "blocks":
-        # phase 1 ("speculate"): per pending vertex its rowptr pair, todo byte
-        # and colour write, per row entry the neighbour id and its slot or
-        # colour; phase 2 ("detect"): the same reads, per entry also the slot
-        # write (entries whose neighbour is in another block: all but ~0.2%
-        # at p = 16384), per pending vertex the todo write
-        sa, sd = golden["blocks_sum_active"], golden["blocks_sum_active_deg"]
-        spec_bytes = sd * 8 + sa * (2 * rp_b + 1 + 4)
-        det_bytes = sd * 12 + sa * (2 * rp_b + 1 + 4 + 1)
     spec_ms, spec_launches = prof["speculate"]
     det_ms, det_launches = prof["detect"]
     kernel = "detect" if det_ms > spec_ms else "speculate"
     k_ms, k_launches, k_bytes = ((det_ms, det_launches, det_bytes) if kernel == "detect"
                                  else (spec_ms, spec_launches, spec_bytes))
+    k_bytes_sw = det_bytes_sw if kernel == "detect" else spec_bytes_sw
     calls = max(1, k_launches // max(1, timed_rounds))
     achieved = k_bytes * calls / (k_ms / 1e3) / 1e9 if k_ms > 0 else None
+    achieved_sw = k_bytes_sw * calls / (k_ms / 1e3) / 1e9 if k_ms > 0 else None
     setting = {"workload": args.workload, "algorithm": algo, "lanes": lanes,
                "blocks_per_cu": G_bpc}
     pmc = read_summary(f"{kernel}_{args.workload}_pmc.txt", setting)
@@ -414,6 +428,9 @@ def graph_record(args, golden, host):
         "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
         "traffic": traffic,
         "alg_bytes_per_launch": k_bytes // max(1, timed_rounds),
+        "alg_bytes_per_launch_at_state_width": k_bytes_sw // max(1, timed_rounds),
+        "state_bytes": sbytes,
+        "frac_at_state_width": round(achieved_sw / HBM_PEAK_GBS, 4) if achieved_sw else None,
         "avg_launch_us": round(k_ms * 1e3 / max(1, k_launches), 2),
         "launches": k_launches,
         "other_kernel": {"kernel": "speculate" if kernel == "detect" else "detect",
