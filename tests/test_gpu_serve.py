@@ -186,3 +186,36 @@ def test_packed_submission(serve, midflight):
         srv.submit_packed(voff, eoff, rpl.cpu(), cil, np.zeros(len(gs)))
     with pytest.raises(ValueError):
         srv.submit_packed(voff, eoff + 5, rpl, cil, np.zeros(len(gs)))
+
+
+def test_step_loop_allocates_nothing(serve):
+    # once built (and warmed by one stream), the server's loop takes no device
+    # memory from the caching allocator and no pinned host memory: the table,
+    # the workspace and every staging buffer were allocated by the constructor
+    gs = graphs(60, 13)
+    voff = np.concatenate([[0], np.cumsum([g.n for g in gs])]).astype(np.int64)
+    eoff = np.concatenate([[0], np.cumsum([g.nnz for g in gs])]).astype(np.int64)
+    rpl = torch.from_numpy(np.concatenate([g.rowptr.astype(np.int32) for g in gs])).cuda()
+    cil = torch.from_numpy(np.concatenate([g.colidx.astype(np.int32) for g in gs])).cuda()
+    srv = serve.Server(budget_bytes=64 << 20, max_slots=16, rounds_per_step=2, keep_colors=False)
+    arrivals = np.sort(np.random.default_rng(5).uniform(0, 0.01, len(gs)))
+    srv.serve_packed(voff, eoff, rpl, cil, arrivals)
+    torch.cuda.synchronize()
+
+    def counts():
+        dev = torch.cuda.memory_stats().get("allocation.all.allocated", 0)
+        host = torch.cuda.host_memory_stats().get("allocation.allocated", 0) \
+            if hasattr(torch.cuda, "host_memory_stats") else 0
+        return dev, host
+
+    before = counts()
+    steps0 = srv.steps
+    jobs = srv.serve_packed(voff, eoff, rpl, cil, arrivals)
+    torch.cuda.synchronize()
+    assert srv.steps > steps0 + 5
+    assert counts() == before
+    assert all(j.finished_at > 0 for j in jobs) and srv.idle()
+    # (the device counter does see an allocation)
+    x = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+    assert counts()[0] > before[0]
+    del x
