@@ -31,7 +31,7 @@ constexpr int kSparseChunk = 32;    // detect: at most this many uncoloured vert
                                     // -> a group of lanes each (at least 2)
 constexpr int kMaxBlocksPerCu = 64; // workgroups per CU of any round kernel (option limit)
 constexpr int kFinishBlocks = 512;  // most workgroups of the finishing pass (one stats pair each)
-constexpr int kDeferRow = 1024;     // a wavefront- or workgroup-class winner with more row entries
+constexpr int kDeferRow = 512;      // a wavefront- or workgroup-class winner with more row entries
                                     // than this left to push queues them for the grid-wide push pass
 constexpr int kPieceEntries = 1024; // row entries of one piece of that pass: one workgroup,
                                     // four entries per thread in flight, one step
