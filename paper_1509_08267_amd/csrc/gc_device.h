@@ -287,21 +287,21 @@ __device__ __forceinline__ bool detect_group4_skip(const int32_t* __restrict__ c
 // first still-uncoloured lower neighbour seen, or of the point where the scan
 // ended when it saw none: every lower neighbour before it is final, and final
 // colours never change, so later rounds (and the winner's pushes) may start
-// there.  Four entries in flight: neighbour ids first, then the states of the
+// there.  Two entries in flight: neighbour ids first, then the states of the
 // lower ones.
 template <typename RP, typename S>
 __device__ __forceinline__ bool detect_lane_skip(const int32_t* __restrict__ colidx,
                                                  const S* __restrict__ st, RP b, RP e, int v,
                                                  int t, int* skip) {
   int first = -1;
-  for (RP k = b + *skip; k < e; k += 4) {
-    int u[4], s[4];
+  for (RP k = b + *skip; k < e; k += 2) {
+    int u[2], s[2];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) u[j] = k + j < e ? colidx[k + j] : INT32_MAX;
+    for (int j = 0; j < 2; ++j) u[j] = k + j < e ? colidx[k + j] : INT32_MAX;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) s[j] = u[j] < v ? (int)st[u[j]] : 0;
+    for (int j = 0; j < 2; ++j) s[j] = u[j] < v ? (int)st[u[j]] : 0;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < 2; ++j) {
       const int off = (int)(k - b) + j;
       if (u[j] >= v) {  // past the lower prefix (or the row's end)
         *skip = first >= 0 ? first : off;
