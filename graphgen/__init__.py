@@ -260,6 +260,20 @@ def empty(n: int) -> CSR:
     return from_edges(n, [])
 
 
+def hub_over_losers(k: int) -> CSR:
+    """k paths x1_i - x2_i - c_i - b_i (ids x1 in [0, k), x2 in [k, 2k), c in
+    [2k, 3k), b in [3k, 4k)), every b_i joined to a hub v = 4k + 1, and v
+    joined to w = 4k.  The hub is the only vertex of high degree, and it
+    commits (round 2) while all k of its lower neighbours b_i are still
+    uncoloured."""
+    edges = []
+    for i in range(k):
+        x1, x2, c, b = i, k + i, 2 * k + i, 3 * k + i
+        edges += [(x1, x2), (x2, c), (c, b), (b, 4 * k + 1)]
+    edges.append((4 * k, 4 * k + 1))
+    return from_edges(4 * k + 2, edges)
+
+
 def random_small(n: int, p: float, rng: np.random.Generator) -> CSR:
     """Tiny G(n, p) for randomized property tests (numpy Generator)."""
     edges = [(i, j) for i in range(n) for j in range(i + 1, n) if rng.random() < p]

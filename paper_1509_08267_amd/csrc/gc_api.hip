@@ -92,9 +92,11 @@ struct gc_ctx {
   uint8_t* seen = nullptr;    // device, n * kPushColors (push algorithm), allocated on first use
   uint8_t* wide = nullptr;    // device, wide_blocks * kWideColors (push algorithm)
   int64_t wide_blocks = 0;    // blocks allocated in `wide`
-  gc::PushTask* tasks = nullptr;  // device, wide_blocks: pushes queued for the grid-wide pass
+  gc::PushTask* tasks = nullptr;  // device, 2 * wide_blocks: pushes queued for the grid-wide pass
   int32_t* widx = nullptr;    // device, n: wide block of each medium/heavy vertex, -1 otherwise
   int32_t* skip = nullptr;    // device, n: final-prefix offset of each row (sorted rows)
+  int32_t* lst = nullptr;     // device, m: lower-neighbour lists of medium and heavy vertices
+  int32_t* llen = nullptr;    // device, n: their lengths
   int32_t* part = nullptr;    // device, cus * kMaxBlocksPerCu: per-workgroup round sizes
   int epoch = 0;              // epoch of the last call's pushed flags (1..255)
   Pinned* host = nullptr;     // pinned
@@ -225,6 +227,10 @@ static KArgs make_args(const gc_ctx* h, int32_t* colors, int light_max) {
   a.wide_clear = (int32_t)h->wide_blocks;
   a.widx = h->widx;
   a.skip = h->skip;
+  // wavefront- and workgroup-class conflict scans keep lists of lower neighbours not yet
+  // seen final (push algorithm, sorted rows)
+  a.lst = (a.push && a.sorted && !a.seq && h->mcount + h->hcount > 0) ? h->lst : nullptr;
+  a.llen = a.lst ? h->llen : nullptr;
   a.part = h->part;
   // long rows of wavefront- and workgroup-class winners are pushed by a
   // grid-wide pass after each detect pass
@@ -293,6 +299,8 @@ static void free_ctx(gc_ctx* h) {
   if (h->tasks) (void)hipFree(h->tasks);
   if (h->widx) (void)hipFree(h->widx);
   if (h->skip) (void)hipFree(h->skip);
+  if (h->lst) (void)hipFree(h->lst);
+  if (h->llen) (void)hipFree(h->llen);
   if (h->part) (void)hipFree(h->part);
   if (h->o_rowptr) (void)hipFree(h->o_rowptr);
   if (h->o_colidx) (void)hipFree(h->o_colidx);
@@ -456,7 +464,7 @@ static bool usable(const Captured& c, int K, int L, int grid, const KArgs& a) {
          b.mlist == a.mlist && b.mcount == a.mcount && b.hlist == a.hlist &&
          b.hcount == a.hcount && b.sorted == a.sorted && b.push == a.push && b.seq == a.seq &&
          b.seen == a.seen && b.flags_by_chunk == a.flags_by_chunk && b.wide == a.wide && b.widx == a.widx && b.skip == a.skip &&
-         b.part == a.part && b.tasks == a.tasks && b.ctrl == a.ctrl;
+         b.lst == a.lst && b.llen == a.llen && b.part == a.part && b.tasks == a.tasks && b.ctrl == a.ctrl;
 }
 
 static float elapsed(hipEvent_t a, hipEvent_t b) {
@@ -665,10 +673,23 @@ extern "C" int gc_color(gc_handle h, int32_t* colors_out, void* stream) {
       h->tasks = nullptr;
       h->wide_blocks = 0;
       hipError_t e = hipMalloc((void**)&h->wide, (size_t)blocks * gc::kWideColors);
-      if (e == hipSuccess) e = hipMalloc((void**)&h->tasks, (size_t)blocks * sizeof(gc::PushTask));
+      if (e == hipSuccess)
+        e = hipMalloc((void**)&h->tasks, 2 * (size_t)blocks * sizeof(gc::PushTask));
       if (e != hipSuccess) return set_err(h, GC_ENOMEM, "wide colour flags: %s", hipGetErrorString(e));
       h->wide_blocks = blocks;
       h->epoch = 0;  // new memory: the next epoch (1) clears every flag
+    }
+    if (blocks > 0 && (h->flags & GC_ROWS_SORTED) && !use_seq(h) && !h->lst) {
+      // lower-neighbour lists: one slot per row entry, one length per vertex
+      hipError_t e = hipMalloc((void**)&h->lst, (size_t)std::max<int64_t>(h->m, 1) * sizeof(int32_t));
+      if (e == hipSuccess)
+        e = hipMalloc((void**)&h->llen, (size_t)std::max<int64_t>(h->n, 1) * sizeof(int32_t));
+      if (e != hipSuccess) {
+        if (h->lst) (void)hipFree(h->lst);
+        h->lst = nullptr;
+        h->llen = nullptr;
+        return set_err(h, GC_ENOMEM, "lower-neighbour lists: %s", hipGetErrorString(e));
+      }
     }
     // a new epoch per call marks this call's flags; flags are cleared on the
     // first call and whenever the 8-bit epoch wraps

@@ -113,10 +113,13 @@ __device__ __forceinline__ size_t flag_index(const KArgs& a, int v, int c) {
 // above the light bound can ever need such a colour).  Plain byte stores:
 // concurrent writers touch different bytes or write the same value.  A
 // neighbour that is already final needs nothing, which the state read skips
-// (about half of all entries).  A group of `step` lanes.
+// (about half of all entries).  A group of `step` lanes.  The neighbour ids
+// are ids[b .. e): the row itself (push_colour) or a list of some of its
+// entries (a wavefront-class vertex's lower-neighbour list).
 template <typename RP, typename S>
-__device__ __forceinline__ void push_colour(const KArgs& a, const S* __restrict__ st, RP b, RP e,
-                                            int t, int epoch, int gl, int step) {
+__device__ __forceinline__ void push_colour_ids(const KArgs& a, const int32_t* __restrict__ ids,
+                                                const S* __restrict__ st, RP b, RP e, int t,
+                                                int epoch, int gl, int step) {
   // four entries per lane in flight: the neighbour ids, then their states,
   // then the stores
   if (t < kPushColors) {
@@ -124,7 +127,7 @@ __device__ __forceinline__ void push_colour(const KArgs& a, const S* __restrict_
     for (; k + 3 * (RP)step < e; k += 4 * (RP)step) {
       int u[4], s[4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) u[j] = a.colidx[k + j * step];
+      for (int j = 0; j < 4; ++j) u[j] = ids[k + j * step];
 #pragma unroll
       for (int j = 0; j < 4; ++j) s[j] = st[u[j]];
 #pragma unroll
@@ -132,7 +135,7 @@ __device__ __forceinline__ void push_colour(const KArgs& a, const S* __restrict_
         if (s[j] < 0) a.seen[flag_index(a, u[j], t)] = (uint8_t)epoch;
     }
     for (; k < e; k += step) {
-      const int u = a.colidx[k];
+      const int u = ids[k];
       if (st[u] < 0) a.seen[flag_index(a, u, t)] = (uint8_t)epoch;
     }
   } else if (t < kPushColors + kWideColors) {
@@ -143,7 +146,7 @@ __device__ __forceinline__ void push_colour(const KArgs& a, const S* __restrict_
     for (; k + 3 * (RP)step < e; k += 4 * (RP)step) {
       int u[4], s[4], w[4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) u[j] = a.colidx[k + j * step];
+      for (int j = 0; j < 4; ++j) u[j] = ids[k + j * step];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         s[j] = st[u[j]];
@@ -154,11 +157,17 @@ __device__ __forceinline__ void push_colour(const KArgs& a, const S* __restrict_
         if (w[j] >= 0 && s[j] < 0) a.wide[(size_t)w[j] * kWideColors + c] = (uint8_t)epoch;
     }
     for (; k < e; k += step) {
-      const int u = a.colidx[k];
+      const int u = ids[k];
       const int w = a.widx[u];
       if (w >= 0 && st[u] < 0) a.wide[(size_t)w * kWideColors + c] = (uint8_t)epoch;
     }
   }
+}
+
+template <typename RP, typename S>
+__device__ __forceinline__ void push_colour(const KArgs& a, const S* __restrict__ st, RP b, RP e,
+                                            int t, int epoch, int gl, int step) {
+  push_colour_ids<RP, S>(a, a.colidx, st, b, e, t, epoch, gl, step);
 }
 
 // First colour in 32..511 not flagged in wide block w, or -1 when all are
@@ -235,6 +244,85 @@ __device__ __forceinline__ bool detect_wave4_skip(const int32_t* __restrict__ co
     }
   }
   *skip = first >= 0 ? first : (int)(e - b);
+  return false;
+}
+
+// A wavefront-class vertex's conflict scan over a list of its lower
+// neighbours (sorted rows, pushed colours).  lst (deg(v) entries, parallel to
+// v's row) holds in its first *len entries lower neighbours that were still
+// uncoloured when last seen; every lower neighbour before row offset *skip is
+// final or on the list.  The list is read whole (the final entries it sheds
+// are the point: a hub's lower prefix interleaves many final neighbours with
+// a few uncoloured ones, which a resume offset alone cannot pass) and
+// compacted in place, then the row is read from *skip, 256 entries per step as
+// four sub-ranges of 64 in row order, adding the uncoloured lower neighbours
+// it passes to the list.  The row part stops at a conflict (left unread at
+// *skip, not listed) or at the first id >= v (*skip then points there, where
+// a winner's pushes to its higher neighbours start).  Returns whether a
+// lower neighbour carries tentative colour t.  Compaction is safe in place:
+// an entry is written at or below the position it was read from, after the
+// whole step's entries are in registers.
+template <typename RP, typename S>
+__device__ __forceinline__ bool detect_wave_list(const int32_t* __restrict__ colidx,
+                                                 const S* __restrict__ st, int32_t* lst, RP b,
+                                                 RP e, int v, int t, int lane, int* skip,
+                                                 int* len) {
+  const uint64_t below = (1ull << lane) - 1;
+  const int n0 = *len;
+  int w = 0;
+  bool lose = false;
+  for (int i0 = 0; i0 < n0; i0 += 2 * kWave) {
+    int u[2], s[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int i = i0 + j * kWave + lane;
+      u[j] = i < n0 ? lst[i] : -1;
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) s[j] = u[j] >= 0 ? (int)st[u[j]] : 0;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      // decode, do not test the sign, for the conflict (as in the row scans)
+      lose |= __ballot(u[j] >= 0 && tent_of(s[j]) == t) != 0;
+      const bool keep = u[j] >= 0 && s[j] < 0;
+      const uint64_t km = __ballot(keep);
+      const int dst = w + __popcll(km & below);
+      if (keep && dst != i0 + j * kWave + lane) lst[dst] = u[j];
+      w += __popcll(km);
+    }
+  }
+  if (lose) {
+    *len = w;
+    return true;
+  }
+  for (RP kb = b + *skip; kb < e; kb += 4 * kWave) {
+    int u[4], s[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const RP k = kb + j * kWave + lane;
+      u[j] = k < e ? colidx[k] : INT32_MAX;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) s[j] = u[j] < v ? (int)st[u[j]] : 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const bool low = u[j] < v;
+      const uint64_t cm = __ballot(low && tent_of(s[j]) == t);
+      const uint64_t stop = cm | __ballot(!low);
+      const int p = stop ? __builtin_ctzll(stop) : kWave;  // lanes before p are passed
+      const bool keep = low && s[j] < 0 && lane < p;
+      const uint64_t km = __ballot(keep);
+      if (keep) lst[w + __popcll(km & below)] = u[j];
+      w += __popcll(km);
+      if (stop) {
+        *skip = (int)(kb - b) + j * kWave + p;
+        *len = w;
+        return (cm >> p) & 1;
+      }
+    }
+  }
+  *skip = (int)(e - b);
+  *len = w;
   return false;
 }
 

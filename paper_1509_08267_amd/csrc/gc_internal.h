@@ -70,8 +70,11 @@ struct Ctrl {
 };
 
 // A winner's pushes handed to the grid-wide push pass: colour t to the row
-// entries [b, e), cut into pieces first .. first + ceil((e - b) / kPieceEntries) - 1
-// of the pass's piece numbering.
+// entries [b, e) (to the list entries lst[b, e) when t carries kFromList),
+// cut into pieces first .. first + ceil((e - b) / kPieceEntries) - 1 of the
+// pass's piece numbering.
+constexpr int32_t kFromList = 1 << 30;
+
 struct PushTask {
   int64_t b;
   int64_t e;
@@ -110,12 +113,17 @@ struct KArgs {
   const int32_t* widx;    // n: index of v's wide flag block, -1 for light vertices
   int32_t* skip;          // n: lower neighbours before this offset of v's row are final
                           // (sorted rows); zeroed by round 1
+  int32_t* lst;           // nnz, parallel to colidx: each medium or heavy vertex's list of lower
+                          // neighbours not yet seen final (detect_wave_list, detect_block_list),
+                          // at its row's offset; null unless the push algorithm runs on sorted
+                          // rows with such vertices
+  int32_t* llen;          // n: length of that list; zeroed by round 1 with skip
   int32_t* part;          // cus * kMaxBlocksPerCu: active vertices of each workgroup of the
                           // last detect pass; the next pass folds them into ctrl->trace
-  PushTask* tasks;        // mcount + hcount: pushes of long rows queued by a detect pass for
-                          // the grid-wide push pass that follows it (push algorithm with
-                          // medium or heavy vertices, not in the persistent kernel; null
-                          // otherwise)
+  PushTask* tasks;        // 2 * (mcount + hcount): pushes of long rows or lists queued by a
+                          // detect pass for the grid-wide push pass that follows it (push
+                          // algorithm with medium or heavy vertices, not in the persistent
+                          // kernel; null otherwise)
   Ctrl* ctrl;
 };
 

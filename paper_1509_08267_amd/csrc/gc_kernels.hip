@@ -47,6 +47,7 @@ struct HeavySmem {
   uint32_t bm[kHeavyWindow / 32];
   uint64_t am[4][kWavesPerBlock], cm[4][kWavesPerBlock], pm[4][kWavesPerBlock];  // detect_block_skip
   int first;
+  int cnt, flag;              // detect_block_list: list length so far, conflict seen
   int wact[kWavesPerBlock];   // per-wave tallies of a detect phase
   int wlost[kWavesPerBlock];
   int wcls[kWavesPerBlock];
@@ -183,6 +184,101 @@ __device__ bool detect_block_skip(const int32_t* __restrict__ colidx, const S* _
   }
   *skip = first >= 0 ? first : (int)(e - b);
   return false;
+}
+
+// detect_wave_list's scan for a heavy vertex by the whole block: the list
+// first, one entry per thread per step, then the row from *skip, a step of
+// 1,024 entries as four sub-ranges of 256 in row order (as in
+// detect_block_skip).  List order carries no meaning, so each wave claims its
+// slots with one LDS atomic; a barrier between a step's reads and its writes
+// keeps the in-place compaction of the list from overwriting an entry not yet
+// read.  Every thread returns the same result, *skip and *len.
+template <typename RP, typename S>
+__device__ bool detect_block_list(const int32_t* __restrict__ colidx, const S* __restrict__ st,
+                                  int32_t* lst, RP b, RP e, int v, int t, int* skip, int* len,
+                                  HeavySmem& sm) {
+  const int tid = threadIdx.x;
+  const int wv = tid / kWave;
+  const int lane = lane_id();
+  const uint64_t below = (1ull << lane) - 1;
+  const int n0 = *len;
+  if (tid == 0) {
+    sm.cnt = 0;
+    sm.flag = 0;
+  }
+  __syncthreads();
+  for (int i0 = 0; i0 < n0; i0 += kBlock) {  // block-uniform
+    const int i = i0 + tid;
+    const int u = i < n0 ? lst[i] : -1;
+    const int sv = u >= 0 ? (int)st[u] : 0;
+    const bool keep = u >= 0 && sv < 0;
+    const uint64_t km = __ballot(keep);
+    const uint64_t cb = __ballot(u >= 0 && tent_of(sv) == t);
+    __syncthreads();  // the step's entries are all read before any is rewritten
+    int base = 0;
+    if (lane == 0) {
+      if (km) base = atomicAdd(&sm.cnt, __popcll(km));
+      if (cb) sm.flag = 1;
+    }
+    base = __shfl(base, 0);
+    if (keep) lst[base + __popcll(km & below)] = u;
+  }
+  __syncthreads();
+  bool lose = sm.flag != 0;
+  if (!lose) {
+    int stop = -1;
+    for (RP kb = b + *skip; kb < e; kb += 4 * kBlock) {  // block-uniform
+      int u[4], sv[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const RP k = kb + j * kBlock + tid;
+        u[j] = k < e ? colidx[k] : INT32_MAX;
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) sv[j] = u[j] < v ? (int)st[u[j]] : 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const bool low = u[j] < v;
+        const uint64_t cm = __ballot(low && tent_of(sv[j]) == t);
+        const uint64_t pm = __ballot(!low);
+        if (lane == 0) {
+          sm.cm[j][wv] = cm;
+          sm.pm[j][wv] = pm;
+        }
+      }
+      __syncthreads();
+      int fc = -1, fp = -1;  // positions within the step, sub-range major
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int w = 0; w < kWavesPerBlock; ++w) {
+          const int pos = j * kBlock + w * kWave;
+          if (fc < 0 && sm.cm[j][w]) fc = pos + __builtin_ctzll(sm.cm[j][w]);
+          if (fp < 0 && sm.pm[j][w]) fp = pos + __builtin_ctzll(sm.pm[j][w]);
+        }
+      // rows ascend, so a conflict precedes the first past entry or there is none
+      const int P = fc >= 0 ? fc : fp >= 0 ? fp : 4 * kBlock;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const bool keep = u[j] < v && sv[j] < 0 && j * kBlock + tid < P;
+        const uint64_t km = __ballot(keep);
+        int base = 0;
+        if (lane == 0 && km) base = atomicAdd(&sm.cnt, __popcll(km));
+        base = __shfl(base, 0);
+        if (keep) lst[base + __popcll(km & below)] = u[j];
+      }
+      __syncthreads();  // the masks are rewritten next step
+      if (P < 4 * kBlock) {
+        stop = (int)(kb - b) + P;
+        lose = fc >= 0;
+        break;
+      }
+    }
+    *skip = stop >= 0 ? stop : (int)(e - b);
+  }
+  *len = sm.cnt;
+  __syncthreads();  // cnt and flag are reset for the next vertex
+  return lose;
 }
 
 // ---------------------------------------------------------- one phase --
@@ -446,7 +542,16 @@ __device__ void medium_phase(const KArgs& a, long wave_gid, long nwaves, Tally& 
         const int t = ~vs;
         bool lose;
         RP pb = b;
-        if (a.sorted) {
+        int ln = 0;
+        if (a.lst) {
+          int sk = a.skip[vv];
+          ln = a.llen[vv];
+          const int sk0 = sk, ln0 = ln;
+          lose = detect_wave_list<RP, S>(a.colidx, st, a.lst + b, b, e, vv, t, lane, &sk, &ln);
+          if (lane == 0 && sk != sk0) a.skip[vv] = sk;
+          if (lane == 0 && ln != ln0) a.llen[vv] = ln;
+          pb = b + sk;
+        } else if (a.sorted) {
           int sk = a.skip[vv];
           lose = detect_wave4_skip<RP, S>(a.colidx, st, b, e, vv, t, lane, &sk);
           if (lane == 0) a.skip[vv] = sk;
@@ -460,6 +565,17 @@ __device__ void medium_phase(const KArgs& a, long wave_gid, long nwaves, Tally& 
           tl.cls |= lose ? 2 : 0;
         }
         if (a.push && !lose) {
+          // with a list, its entries are the lower neighbours still uncoloured and
+          // the row from pb holds the higher ones
+          if (ln > 0) {
+            if (a.tasks && ln > kDeferRow) {
+              if (lane == 0) queue_push(a, (int64_t)b, (int64_t)b + ln, t | kFromList);
+            } else {
+              // the list entries were written by other lanes of this wave
+              __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+              push_colour_ids<RP, S>(a, a.lst, st, b, b + ln, t, epoch, lane, kWave);
+            }
+          }
           if (a.tasks && e - pb > (RP)kDeferRow) {
             // a long row: the push pass after this one spreads it over the grid
             if (lane == 0) queue_push(a, pb, e, t);
@@ -589,7 +705,17 @@ __device__ void heavy_phase(const KArgs& a, long blk, long nblk, Tally& tl, Heav
       const int t = ~s;
       bool lose;
       RP pb = b;
-      if (a.sorted) {
+      int ln = 0;
+      if (a.lst) {
+        int sk = a.skip[v];
+        ln = a.llen[v];
+        lose = detect_block_list<RP, S>(a.colidx, st, a.lst + b, b, e, v, t, &sk, &ln, sm);
+        if (threadIdx.x == 0) {
+          a.skip[v] = sk;
+          a.llen[v] = ln;
+        }
+        pb = b + sk;
+      } else if (a.sorted) {
         int sk = a.skip[v];
         lose = detect_block_skip<RP, S>(a.colidx, st, b, e, v, t, &sk, sm);
         if (threadIdx.x == 0) a.skip[v] = sk;
@@ -603,6 +729,16 @@ __device__ void heavy_phase(const KArgs& a, long blk, long nblk, Tally& tl, Heav
         tl.cls |= lose ? 4 : 0;
       }
       if (a.push && !lose) {
+        // with a list, its entries are the lower neighbours still uncoloured
+        // and the row from pb holds the higher ones
+        if (ln > 0) {
+          if (a.tasks && ln > kDeferRow) {
+            if (threadIdx.x == 0) queue_push(a, (int64_t)b, (int64_t)b + ln, t | kFromList);
+          } else {
+            push_colour_ids<RP, S>(a, a.lst, st, b, b + ln, t, a.ctrl->epoch.v, threadIdx.x,
+                                   kBlock);
+          }
+        }
         if (a.tasks && e - pb > (RP)kDeferRow) {
           // a hub's long row: its pushes are spread over the whole grid by
           // the pass that follows, instead of one workgroup walking it
@@ -761,13 +897,14 @@ __global__ __launch_bounds__(kBlock) void k_push_tasks(KArgs a) {
       else hi = mid - 1;
     }
     const PushTask x = a.tasks[lo];
-    const int t = x.t;
+    const int t = x.t & ~kFromList;
+    const int32_t* __restrict__ ids = (x.t & kFromList) ? a.lst : a.colidx;
     const int64_t k0 = x.b + (p - x.first) * (int64_t)kPieceEntries;
     const int64_t k1 = k0 + kPieceEntries < x.e ? k0 + kPieceEntries : x.e;
     for (int64_t k = k0 + threadIdx.x; k < k1; k += 4 * kBlock) {
       int u[4], sv[4], w[4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) u[j] = k + j * kBlock < k1 ? a.colidx[k + j * kBlock] : -1;
+      for (int j = 0; j < 4; ++j) u[j] = k + j * kBlock < k1 ? ids[k + j * kBlock] : -1;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         sv[j] = u[j] >= 0 ? (int)st[u[j]] : 0;
@@ -801,6 +938,7 @@ __global__ __launch_bounds__(kBlock) void k_round1_sorted(KArgs a) {
     const bool lose = e > b && a.colidx[b] < v;
     st[v] = lose ? (S)-1 : (S)0;
     a.skip[v] = 0;
+    if (a.llen) a.llen[v] = 0;
     tl.lost += lose;
     tl.cls |= lose ? 7 : 0;  // (any class may have lost: the closed form does not tell)
     tl.active += 1;
@@ -834,6 +972,7 @@ __global__ __launch_bounds__(kBlock) void k_round1_sorted_push(KArgs a) {
       const bool lose = e > b && a.colidx[b] < v;
       st[v] = lose ? (S)-1 : (S)0;
       a.skip[v] = 0;
+      if (a.llen) a.llen[v] = 0;
       tl.lost += lose;
       tl.cls |= lose ? 7 : 0;  // (any class may have lost: the closed form does not tell)
       tl.active += 1;
@@ -859,6 +998,7 @@ __global__ void k_fill_tent0(KArgs a) {
   for (long v = tid; v < a.n; v += nth) {
     st[v] = init;
     a.skip[v] = 0;
+    if (a.llen) a.llen[v] = 0;
   }
 }
 
@@ -1022,6 +1162,7 @@ __global__ __launch_bounds__(kBlock) void k_persistent(KArgs a, int max_rounds) 
     for (long v = tid; v < a.n; v += nth) {
       st[v] = init;
       a.skip[v] = 0;
+      if (a.llen) a.llen[v] = 0;
     }
   }
   if (!grid_barrier(a.ctrl, epoch)) return;

@@ -108,6 +108,22 @@ def test_forced_medium_and_heavy_paths(gc):
                               algorithm=algo)
 
 
+@pytest.mark.parametrize("k", [300, 600])
+def test_hub_lists_and_their_pushes(gc, k):
+    # The hub commits in round 2 while its k lower neighbours are all still
+    # uncoloured: its conflict scan lists every one of them, and its pushes
+    # to them come from that list (queued for the grid-wide push pass when
+    # longer than a row the detect pass pushes itself, pushed inline by the
+    # persistent kernel).  A lost push would let them take the hub's colour.
+    g = graphgen.hub_over_losers(k)
+    ref = oracle.rsc(g.rowptr, g.colidx)
+    for medium, heavy in [(16, 100000), (16, 200)]:  # hub: wavefront class, then workgroup class
+        for mode in ("host", "graph", "persistent"):
+            print(f"[case] hub k={k} medium={medium} heavy={heavy} mode={mode}", flush=True)
+            assert_parity(gc, g, ref, mode=mode, medium_degree=medium, heavy_degree=heavy,
+                          algorithm="push")
+
+
 def test_multiword_colour_windows(gc):
     # K_n needs colours up to n-1: beyond 64 (light/medium window) and with
     # heavy_degree small, beyond nothing; K_4200 would exceed the 4096-bit

@@ -118,6 +118,21 @@ def test_crown_graph_first_fit_worst_case(k):
         assert ref_py.chromatic_number(adj(graphgen.crown(k))) == 2
 
 
+@pytest.mark.parametrize("k", [1, 3, 600])
+def test_hub_over_losers_worked_rounds(k):
+    # Paths x1 - x2 - c - b, every b joined to the hub v, and v to w (ids in
+    # that order, v last).  Round 1: x1 and w have no lower neighbour and
+    # keep 0; x2, c, b and v lose to a lower neighbour also trying 0.  Round
+    # 2: x2 tries 1 (x1 has 0) and keeps it; c and b try 0 (no final
+    # neighbour), c keeps it over x2's 1, b loses to c; v tries 1 (w has 0)
+    # and keeps it, since every b (lower) tries 0.  Round 3: b sees 0 on c and
+    # 1 on v and takes 2.
+    r = run(graphgen.hub_over_losers(k))
+    assert list(r.colors) == [0] * k + [1] * k + [0] * k + [2] * k + [0, 1]
+    assert r.rounds == 3
+    assert list(r.trace[:, 0]) == [4 * k + 2, 3 * k + 1, k]
+
+
 @pytest.mark.parametrize("n", [1, 5, 100])
 def test_empty_graph(n):
     r = run(graphgen.empty(n))
