@@ -94,7 +94,9 @@ enum gc_flags {
  * array of 1/2/4 bytes per vertex, a 4-byte resume offset per vertex,
  * worklists and counters; on the first push-algorithm call 32 flag bytes per
  * vertex plus 480 per vertex handled by a whole wave or workgroup, see
- * GC_OPT_MEDIUM_DEGREE) and a small pinned host block; it synchronises
+ * GC_OPT_MEDIUM_DEGREE, and, on sorted rows with such vertices, 4 bytes per
+ * CSR entry and per vertex for their lower-neighbour lists) and a small
+ * pinned host block; it synchronises
  * `stream` before returning.  The handle belongs to the device current at
  * this call.
  * Returns GC_OK, GC_EINVAL, GC_ENOMEM, GC_ETOOBIG or GC_EDEVICE.
