@@ -51,30 +51,47 @@ from . import gc
 
 
 class ArenaAllocator:
-    """First-fit allocator over [0, capacity) in units of int32 words, with
-    coalescing of freed neighbours."""
+    """Best-fit allocator over [0, capacity) in units of int32 words: a
+    request takes the smallest free block that holds it (the lowest such on
+    ties), and freed neighbours coalesce.  Free blocks are indexed twice,
+    by start and by (size, start), in sorted lists searched by bisection,
+    so a call costs a binary search and a list insertion whatever the
+    number of free blocks (a first-fit walk over a few thousand fragments
+    once held a serving step for over 100 ms)."""
 
     def __init__(self, capacity: int):
         self.capacity = int(capacity)
-        self._starts = [0] if capacity > 0 else []   # free blocks, sorted by start
-        self._sizes = {0: self.capacity} if capacity > 0 else {}
+        self._starts = []      # free blocks, sorted by start
+        self._sizes = {}       # start -> size
+        self._by_size = []     # (size, start), sorted
         self.used = 0
+        if self.capacity > 0:
+            self._add(0, self.capacity)
+
+    def _add(self, start: int, size: int):
+        bisect.insort(self._starts, start)
+        self._sizes[start] = size
+        bisect.insort(self._by_size, (size, start))
+
+    def _remove(self, start: int) -> int:
+        size = self._sizes.pop(start)
+        del self._starts[bisect.bisect_left(self._starts, start)]
+        del self._by_size[bisect.bisect_left(self._by_size, (size, start))]
+        return size
 
     def alloc(self, size: int):
         size = int(size)
         if size <= 0:
             raise ValueError("allocation size must be positive")
-        for i, s in enumerate(self._starts):
-            have = self._sizes[s]
-            if have >= size:
-                del self._sizes[s]
-                self._starts.pop(i)
-                if have > size:
-                    self._starts.insert(i, s + size)
-                    self._sizes[s + size] = have - size
-                self.used += size
-                return s
-        return None
+        i = bisect.bisect_left(self._by_size, (size, -1))
+        if i == len(self._by_size):
+            return None
+        have, s = self._by_size[i]
+        self._remove(s)
+        if have > size:
+            self._add(s + size, have - size)
+        self.used += size
+        return s
 
     def release(self, start: int, size: int):
         start, size = int(start), int(size)
@@ -85,20 +102,54 @@ class ArenaAllocator:
             p = self._starts[i - 1]
             if p + self._sizes[p] > start:
                 raise ValueError("double free or overlapping release")
-        self._starts.insert(i, start)
-        self._sizes[start] = size
         self.used -= size
-        if i + 1 < len(self._starts) and start + size == self._starts[i + 1]:
-            nxt = self._starts.pop(i + 1)
-            self._sizes[start] += self._sizes.pop(nxt)
+        if i < len(self._starts) and start + size == self._starts[i]:
+            size += self._remove(self._starts[i])
         if i > 0:
             prv = self._starts[i - 1]
             if prv + self._sizes[prv] == start:
-                self._sizes[prv] += self._sizes.pop(start)
-                self._starts.pop(i)
+                size += self._remove(prv)
+                start = prv
+        self._add(start, size)
+
+    def release_many(self, starts, sizes):
+        """Free several blocks at once (a serving step's finished jobs): the
+        free list and the released blocks are merged, checked for overlap
+        and coalesced in one sorted pass, and both indexes rebuilt; a
+        handful of blocks take the per-block path instead."""
+        st = np.asarray(starts, np.int64).ravel()
+        sz = np.asarray(sizes, np.int64).ravel()
+        if st.size != sz.size:
+            raise ValueError("starts and sizes differ in length")
+        if st.size < 32:
+            for a, b in zip(st.tolist(), sz.tolist()):
+                self.release(a, b)
+            return
+        if np.any(sz <= 0) or np.any(st < 0) or np.any(st + sz > self.capacity):
+            raise ValueError("release outside the arena")
+        nf = len(self._starts)
+        fs = np.fromiter(self._starts, np.int64, nf)
+        fz = np.fromiter((self._sizes[a] for a in self._starts), np.int64, nf)
+        allst = np.concatenate([fs, st])
+        allsz = np.concatenate([fz, sz])
+        order = np.argsort(allst, kind="stable")
+        allst, allsz = allst[order], allsz[order]
+        ends = allst + allsz
+        if np.any(ends[:-1] > allst[1:]):
+            raise ValueError("double free or overlapping release")
+        head = np.ones(allst.size, bool)
+        head[1:] = ends[:-1] != allst[1:]          # a block not touching the previous one
+        first = np.nonzero(head)[0]
+        rs = allst[first]
+        rz = np.add.reduceat(allsz, first)
+        by = np.lexsort((rs, rz))
+        self._starts = rs.tolist()
+        self._sizes = dict(zip(self._starts, rz.tolist()))
+        self._by_size = list(zip(rz[by].tolist(), rs[by].tolist()))
+        self.used -= int(sz.sum())
 
     def largest_free(self) -> int:
-        return max(self._sizes.values(), default=0)
+        return self._by_size[-1][0] if self._by_size else 0
 
     def free_blocks(self):
         return [(s, self._sizes[s]) for s in self._starts]
@@ -179,6 +230,8 @@ class Server:
         self.backlog_rounds_per_step = int(4 * rounds_per_step if backlog_rounds_per_step is None
                                            else backlog_rounds_per_step)
         self.backlog_steps = 0             # steps launched with the backlog's round count
+        self.max_wait_s = 0.0              # longest wait for a step's completion event
+        self.max_host_s = 0.0              # longest host time of one step() outside that wait
         self.keep_colors = keep_colors
         self.compute = torch.cuda.Stream(self.device)
         self.copy = torch.cuda.Stream(self.device)
@@ -197,6 +250,7 @@ class Server:
         self._pending_copy = None          # event of the last admission copy
         self._keep = []                    # staging tensors alive until their copy has run
         self._resident = 0                 # admitted and not yet finished
+        self._waited = 0.0                 # event waits of the current step()
         self.clock = time.perf_counter
         gc.desc_array([])                  # the record layout (gc.DESC_DTYPE)
         # Pinned host staging, allocated once: a ring of PIPELINE + 1 sets,
@@ -429,8 +483,10 @@ class Server:
 
     def _complete_oldest(self) -> int:
         st = self.inflight.popleft()
+        t0 = self.clock()
         st.event.synchronize()
         now = self.clock()
+        self._waited += now - t0
         table = st.table_host.numpy().view(gc.DESC_DTYPE)
         # jobs found finished at the previous completion were still listed by
         # this step; it has run, so their memory can be reused now
@@ -439,13 +495,15 @@ class Server:
         ids = st.row_ids
         rows = np.nonzero((table["active"] == 0) & ~self.finished[ids])[0]
         finished = []
-        for i in rows:
-            job = self.jobs[int(ids[i])]
-            job.rounds = int(table["rounds"][i])
+        jobs, done, number = self.jobs, self.done, st.number
+        # whole columns read once: a step can finish thousands of jobs
+        for jid, r in zip(ids[rows].tolist(), table["rounds"][rows].tolist()):
+            job = jobs[jid]
+            job.rounds = r
             job.finished_at = now
-            job.finished_step = st.number
+            job.finished_step = number
             finished.append(job)
-            self.done[job.id] = job
+            done[jid] = job
         if rows.size:
             self.finished[ids[rows]] = True
             self.dead += rows.size
@@ -475,8 +533,8 @@ class Server:
             for j in jobs:
                 j.colors = flat[pos:pos + j.n]
                 pos += j.n
+        self.alloc.release_many([j.offset for j in jobs], [j.words for j in jobs])
         for j in jobs:
-            self.alloc.release(j.offset, j.words)
             j.offset = -1
             j.rowptr = j.colidx = None
             del self.jobs[j.id]
@@ -485,7 +543,9 @@ class Server:
         """Admit what fits, queue one step over every resident job (at most
         rounds_per_step rounds each), and wait for the oldest step in flight
         once the pipeline is full.  Returns the number of jobs found finished."""
-        new = self._admit(self.clock())
+        t0 = self.clock()
+        self._waited = 0.0
+        new = self._admit(t0)
         finished = 0
         if self._resident > 0 and (new or self.row_ids.size > self.dead):
             self._launch(new)
@@ -493,7 +553,15 @@ class Server:
                 finished += self._complete_oldest()
         elif self.inflight:
             finished += self._complete_oldest()
+        self.max_wait_s = max(self.max_wait_s, self._waited)
+        self.max_host_s = max(self.max_host_s, self.clock() - t0 - self._waited)
         return finished
+
+    def reset_peaks(self):
+        """Zero max_wait_s and max_host_s (for instance between two
+        measured arrival streams on one long-lived server)."""
+        self.max_wait_s = 0.0
+        self.max_host_s = 0.0
 
     def run_until_idle(self, max_steps: int = 1_000_000):
         # Python's cyclic garbage collector is paused while the loop runs: a
