@@ -265,21 +265,25 @@ class Server:
                            for _ in range(ring)]
         self._pin_rows = [torch.empty(self.max_slots * rec, dtype=torch.uint8, pin_memory=True)
                           for _ in range(ring)]
-        self._pin_keep = [torch.empty(self.max_slots, dtype=torch.int64, pin_memory=True)
-                          for _ in range(ring)]
+        # descriptors of the table compaction: one segment per run of kept rows
+        self._pin_kdesc = [torch.empty(self.max_slots * 4, dtype=torch.int64, pin_memory=True)
+                           for _ in range(ring)]
+        if rec % 4:
+            raise RuntimeError("descriptor records must be whole int32 words")
         self._pin_desc = [torch.empty(2 * self.max_slots * 4, dtype=torch.int64, pin_memory=True)
                           for _ in range(ring)]
         # Device buffers, allocated once as well (a new size class inside the
         # loop reached the device allocator, and one step's set-up took 64 ms,
         # measured): the descriptor table in one of two buffers (a step's
-        # dropped rows are gathered into the other; both are used only on
-        # the compute stream, in order), the gather's indices, the copy
-        # descriptors (used only on the copy stream) and the step workspace.
+        # kept rows are copied into the other; both are used only on the
+        # compute stream, in order), the descriptors of that copy (compute
+        # stream) and of the admission copies (copy stream), and the step
+        # workspace.
         self._dtab = [torch.empty(self.max_slots * rec, dtype=torch.uint8, device=self.device)
                       for _ in range(2)]
         self._dcur = 0                     # the buffer holding the table
         self._rows = 0                     # rows of the table
-        self._didx = torch.empty(self.max_slots, dtype=torch.int64, device=self.device)
+        self._dkdesc = torch.empty(self.max_slots * 4, dtype=torch.int64, device=self.device)
         self._ddesc = torch.empty(2 * self.max_slots * 4, dtype=torch.int64, device=self.device)
         self._ws = torch.empty(max(gc.gc_batch_step_workspace_bytes(self.max_slots, 0), 1),
                                dtype=torch.uint8, device=self.device)
@@ -433,15 +437,20 @@ class Server:
                 self.row_ids = self.row_ids[keep]
                 self.dead = 0
                 if keep.size:
-                    # (pinned source, asynchronous copy: nothing here waits
-                    # for the step in flight)
-                    h = self._pin_keep[slot][:keep.size]
-                    h.numpy()[:] = keep
-                    self._didx[:keep.size].copy_(h, non_blocking=True)
-                    cur = self._dtab[self._dcur].view(self.max_slots, rec)
-                    nxt = self._dtab[1 - self._dcur].view(self.max_slots, rec)
-                    torch.index_select(cur[:self._rows], 0, self._didx[:keep.size],
-                                       out=nxt[:keep.size])
+                    # the kept rows move to the other buffer, one segment per
+                    # run of consecutive rows, with the library's segment copy
+                    # (descriptors staged in the pinned ring: nothing here
+                    # waits for the step in flight).  torch.index_select did
+                    # this before and once held the host for 149 ms inside
+                    # the call (measured), which every job in flight waited out.
+                    brk = np.flatnonzero(np.diff(keep) != 1) + 1
+                    first = np.concatenate(([0], brk))
+                    last = np.concatenate((brk, [keep.size]))
+                    gc.copy_segments_raw(
+                        self._dtab[self._dcur].data_ptr() + keep[first] * rec,
+                        self._dtab[1 - self._dcur].data_ptr() + first * rec,
+                        (last - first) * (rec // 4), self.device, stream=self.compute,
+                        host_buf=self._pin_kdesc[slot], dev_buf=self._dkdesc)
                     self._dcur = 1 - self._dcur
                 self._rows = int(keep.size)
             if new:
